@@ -1,0 +1,166 @@
+/*
+ * dqj.h -- C ABI of the MI355X (gfx950) dual-quaternion Julia ray-march library.
+ *
+ * What the library computes (Kenwright, "Dual-Quaternion Julia Fractals"):
+ *   - a dual quaternion zeta = q_r + q_d e is 8 reals [r0 r1 r2 r3 | d0 d1 d2 d3],
+ *     slot 0 of each quaternion its scalar (Eq. quatsq squares its first slot as the
+ *     scalar; Appendix, "Quaternion Operations" and "Dual-Quaternion Operations");
+ *   - the iteration zeta_{n+1} = zeta_n^2 + c (Eq. dqjulia2), with
+ *     (a + e b)^2 = a^2 + e (a b + b a) (the Appendix product rule with e^2 = 0);
+ *   - escape when ||zeta||^2 > R^2 (strict), tested after every update; a point that
+ *     has not escaped after max_iter updates is inside (section "Practical
+ *     Considerations");
+ *   - a 3D slice zeta_0 = O + X U + Y V + Z W through R^8 (section "Dimension
+ *     Reduction");
+ *   - per pixel, a ray clipped to a bounding box and marched in march_steps equal
+ *     steps (section "Ray-Marching"); the first inside sample k* is refined by
+ *     bisect_steps bisections of [t_{k*-1}, t_{k*}] (hit = final midpoint; k* = 0
+ *     gives the box entry point); the normal is the normalised central difference
+ *     (step normal_h) of the escape potential ln(||z_m||^2) 2^-m, m the escape
+ *     index; shade = clamp(k_a + k_d max(0, n.l), 0, 1) (section
+ *     "Lighting/Illumination", Eq. phong, ambient and diffuse terms).
+ *
+ * Conventions for every call:
+ *   - Parameter records are read during the call and copied; the caller keeps
+ *     ownership. Output buffers are DEVICE pointers owned by the caller; they must
+ *     stay valid until the stream has executed the work (render calls) or until
+ *     poll/wait reports a final status (serve calls).
+ *   - Render calls validate synchronously, enqueue on the caller's HIP stream
+ *     (NULL = the null stream) and return without waiting. A device fault shows up
+ *     as DQJ_E_DEVICE on a later call.
+ *   - No C++ exception crosses this boundary. On any non-OK status a description is
+ *     available from dqj_last_error() on the same thread.
+ *   - Images are H x W row-major, row 0 at the top, pixel (i, j) at index j*W + i.
+ */
+#ifndef DQJ_H
+#define DQJ_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dqj_status;
+enum {
+  DQJ_OK = 0,
+  DQJ_PENDING = 1,
+  DQJ_E_INVALID = -1,      /* a parameter failed validation */
+  DQJ_E_NOMEM = -2,        /* device or host allocation failed */
+  DQJ_E_BUDGET = -3,       /* request alone exceeds the server's HBM budget */
+  DQJ_E_QUEUE_FULL = -4,   /* server pending queue is full */
+  DQJ_E_DEVICE = -5,       /* HIP runtime or kernel error */
+  DQJ_E_TIMEOUT = -6,
+  DQJ_E_CANCELLED = -7,
+  DQJ_E_UNSUPPORTED = -8,  /* no gfx950 device, or a mode this build does not offer */
+  DQJ_E_STATE = -9         /* call not valid in the object's current state */
+};
+
+/* Escape norm. EUCLID8 (default): sum of all 8 squares -- the series must stay
+ * bounded in every component (section "Dual-Quaternion Julia Sets").
+ * REALPART: squares of the real quaternion only -- the dual-number modulus
+ * |a + b e| = |a| of the Introduction. */
+enum { DQJ_NORM_EUCLID8 = 0, DQJ_NORM_REALPART = 1 };
+
+/* Arithmetic of the render. FP32: every step in FP32. SPLIT: march in packed FP16,
+ * bisection/normal/shade in FP32, rays whose FP32 in/out sequence around the FP16
+ * crossing is ambiguous re-done in FP64. FP64: every step in FP64 on the GPU. */
+enum { DQJ_PREC_FP32 = 0, DQJ_PREC_SPLIT = 1, DQJ_PREC_FP64 = 2 };
+
+typedef struct dqj_params {
+  uint32_t struct_size;        /* = sizeof(dqj_params); other values -> DQJ_E_INVALID */
+  double c[8];                 /* Julia constant [r0..r3 | d0..d3] */
+  double slice_origin[8];      /* O */
+  double slice_axes[3][8];     /* U, V, W: world X, Y, Z -> R^8 */
+  double box_min[3], box_max[3];   /* march region, box_min < box_max */
+  double eye[3], target[3], up[3]; /* pinhole camera; up not parallel to target-eye */
+  double fov_y_deg;            /* vertical field of view, (0, 180) */
+  int32_t width, height;       /* 1..16384 */
+  int32_t max_iter;            /* N, 1..4096 */
+  int32_t march_steps;         /* S >= 1: S+1 samples t_k = t0 + k (t1-t0)/S */
+  int32_t bisect_steps;        /* B >= 0 (0..64) */
+  double escape_radius;        /* R > 0: escape iff ||z||^2 > R^2 */
+  int32_t norm;                /* DQJ_NORM_* */
+  int32_t precision;           /* DQJ_PREC_* */
+  int32_t fp64_window;         /* SPLIT only: FP32 verify window +-w samples (1..8), default 2 */
+  double normal_h;             /* central-difference step, > 0 */
+  double light_dir[3];         /* direction towards the light (normalised by the library) */
+  double k_ambient, k_diffuse;
+} dqj_params;
+
+/* Per-pixel ray flags written to dqj_frame_out.flags (bit set). */
+enum {
+  DQJ_FLAG_BOX = 1,       /* ray meets the box */
+  DQJ_FLAG_HIT = 2,       /* a sample was inside */
+  DQJ_FLAG_FP64 = 4,      /* SPLIT: ray was re-done in FP64 */
+  DQJ_FLAG_FALLBACK = 8   /* normal fell back to -d (zero or non-finite gradient) */
+};
+
+typedef struct dqj_frame_out {
+  uint32_t struct_size;     /* = sizeof(dqj_frame_out) */
+  uint8_t *mask;            /* required: 1 hit, 0 miss */
+  float *depth;             /* required: ray parameter t of the hit (distance), +inf on miss */
+  float *shade;             /* required: [0, 1], 0 on miss */
+  uint8_t *image8;          /* optional: floor(255 shade + 1/2) */
+  float *normal;            /* optional: 3 floats per pixel, 0 on miss */
+  int32_t *first_hit;       /* optional: k* or -1 */
+  uint8_t *flags;           /* optional: DQJ_FLAG_* */
+  unsigned long long *iters;/* optional, one counter: += DQ updates the method ran for the
+                               frame (march through k*, bisection, 6 normal samples) */
+} dqj_frame_out;
+
+/* Render one frame (section "Ray-Marching" through "Lighting/Illumination").
+ * precision FP32 and SPLIT are offered. */
+dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *hip_stream);
+
+/* Render n frames (params[i] -> outs[i]) in one persistent launch over a global
+ * (frame, tile) queue. All frames must share precision. */
+dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
+                            void *hip_stream);
+
+/* Work schedule of the persistent kernels (chosen by dqj_autotune, or by hand).
+ * Any field 0 = library default. */
+typedef struct dqj_schedule {
+  uint32_t struct_size;
+  int32_t tile_w, tile_h;      /* pixels per tile handed to one wave (tile_w*tile_h <= 4096) */
+  int32_t waves_per_block;     /* 1..16 (block = 64 * waves_per_block threads) */
+  int32_t blocks_per_cu;       /* persistent grid = CUs * blocks_per_cu */
+} dqj_schedule;
+
+/* A batch captured once into a HIP graph and replayed: the parameter table stays
+ * resident in device memory, each replay is one queue reset plus one persistent
+ * kernel. sched may be NULL (autotune cache entry if present, else default). */
+typedef struct dqj_batch_plan dqj_batch_plan;
+dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
+                                 const dqj_schedule *sched, void *hip_stream,
+                                 dqj_batch_plan **plan);
+dqj_status dqj_batch_plan_launch(dqj_batch_plan *plan, void *hip_stream);
+dqj_status dqj_batch_plan_destroy(dqj_batch_plan *plan);   /* waits for its work */
+
+/* Classify n points of R^8 (device, row-major n x 8 floats for FP32 or doubles for
+ * FP64; precision DQJ_PREC_FP32 or DQJ_PREC_FP64) with params->c, max_iter,
+ * escape_radius and norm. escape_iter[i] = escape index 1..N, or 0 when inside;
+ * final_norm2[i] = ||z_m||^2 as float. Test and debugging entry point. */
+dqj_status dqj_classify_points(const void *pts_dev, int32_t n, int32_t precision,
+                               const dqj_params *params, int32_t *escape_iter_dev,
+                               float *final_norm2_dev, void *hip_stream);
+
+typedef struct dqj_device_info {
+  uint32_t struct_size;
+  char arch[64];               /* e.g. "gfx950:sramecc+:xnack-" */
+  int32_t compute_units;
+  int32_t clock_khz;           /* peak engine clock reported by the runtime */
+  int32_t memory_clock_khz;
+  uint64_t total_mem_bytes;
+  double fp32_vector_peak_tflops;   /* 256 flop/clk/CU (packed) x CUs x clock */
+  double fp32_unpacked_peak_tflops; /* 128 flop/clk/CU x CUs x clock */
+} dqj_device_info;
+dqj_status dqj_device_info_get(int32_t device, dqj_device_info *out);
+
+const char *dqj_last_error(void);          /* thread-local text of the last non-OK status */
+const char *dqj_status_str(dqj_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,379 @@
+// dqj_oracle.cpp -- plain FP64 CPU oracle (test infrastructure only; see dqj_oracle.h).
+//
+// Built with -O2 -ffp-contract=off -fno-fast-math: every product and sum is rounded
+// on its own, IEEE round-to-nearest, so inf/NaN behave as the C standard says.
+// Nothing here is blocked, fused or reordered beyond what each cited passage states.
+#include "dqj_oracle.h"
+
+#include <math.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// Quaternion operations (Appendix, "Quaternion Operations"). A quaternion is the
+// 4-tuple (s, v) = (q0, q1, q2, q3): slot 0 is the scalar s, slots 1..3 the
+// vector v on the i, j, k axes.
+// ---------------------------------------------------------------------------
+
+// multiplication: [s1, v1][s2, v2] = [s1 s2 - v1.v2, s1 v2 + s2 v1 + v1 x v2]
+void dqjo_quat_mul(const double a[4], const double b[4], double out[4]) {
+  const double s1 = a[0], s2 = b[0];
+  const double v1[3] = {a[1], a[2], a[3]};
+  const double v2[3] = {b[1], b[2], b[3]};
+  const double dot = v1[0] * v2[0] + v1[1] * v2[1] + v1[2] * v2[2];
+  const double cross[3] = {v1[1] * v2[2] - v1[2] * v2[1],
+                           v1[2] * v2[0] - v1[0] * v2[2],
+                           v1[0] * v2[1] - v1[1] * v2[0]};
+  double r[4];
+  r[0] = s1 * s2 - dot;
+  for (int k = 0; k < 3; ++k) r[k + 1] = s1 * v2[k] + s2 * v1[k] + cross[k];
+  memcpy(out, r, sizeof r);
+}
+
+// Eq. quatsq: q^2 = (x^2 - y^2 - z^2 - w^2, 2xy, 2xz, 2xw), x the scalar slot.
+void dqjo_quat_square_eq(const double q[4], double out[4]) {
+  const double x = q[0], y = q[1], z = q[2], w = q[3];
+  double r[4];
+  r[0] = x * x - y * y - z * z - w * w;
+  r[1] = 2.0 * x * y;
+  r[2] = 2.0 * x * z;
+  r[3] = 2.0 * x * w;
+  memcpy(out, r, sizeof r);
+}
+
+// ---------------------------------------------------------------------------
+// Dual-quaternion operations (Appendix, "Dual-Quaternion Operations").
+// zeta = q_r + q_d e, stored as [q_r | q_d] (8 doubles), e^2 = 0 (Introduction,
+// "Geometric Properties of Complex & Dual Numbers").
+// ---------------------------------------------------------------------------
+
+// addition, the printed "q_r1 + q_r1" read as q_r1 + q_r2.
+void dqjo_dq_add(const double x[8], const double y[8], double out[8]) {
+  double r[8];
+  for (int k = 0; k < 8; ++k) r[k] = x[k] + y[k];
+  memcpy(out, r, sizeof r);
+}
+
+// multiplication, the printed "q_r1 + q_r2" of the real part read as q_r1 q_r2:
+// (q_r1 + q_d1 e)(q_r2 + q_d2 e) = q_r1 q_r2 + (q_r1 q_d2 + q_d1 q_r2) e.
+void dqjo_dq_mul(const double x[8], const double y[8], double out[8]) {
+  double real[4], t1[4], t2[4], r[8];
+  dqjo_quat_mul(x, y, real);          // q_r1 q_r2
+  dqjo_quat_mul(x, y + 4, t1);        // q_r1 q_d2
+  dqjo_quat_mul(x + 4, y, t2);        // q_d1 q_r2
+  for (int k = 0; k < 4; ++k) {
+    r[k] = real[k];
+    r[k + 4] = t1[k] + t2[k];
+  }
+  memcpy(out, r, sizeof r);
+}
+
+// zeta^2 = zeta zeta = a a + (a b + b a) e. The printed component-wise form
+// q_a^2 + q_b^2 e is not what the product rule gives; the product rule is taken.
+void dqjo_dq_square(const double z[8], double out[8]) { dqjo_dq_mul(z, z, out); }
+
+static void dq_step(const double z[8], const double c[8], double out[8]) {
+  double sq[8];
+  dqjo_dq_square(z, sq);
+  dqjo_dq_add(sq, c, out);
+}
+
+void dqjo_orbit(const double z0[8], const double c[8], int32_t n, double out[8]) {
+  double z[8];
+  memcpy(z, z0, sizeof z);
+  for (int32_t i = 0; i < n; ++i) dq_step(z, c, z);
+  memcpy(out, z, sizeof z);
+}
+
+// Escape norm. Default: the sum of the squares of all 8 components (the series
+// must stay bounded in every component, section "Dual-Quaternion Julia Sets", and
+// the estimator uses a quaternion calculation for the real and for the dual part,
+// section "Experimental Results"). Alternative: the real quaternion's squares only
+// (the dual-number modulus |a + b e| = |a| of the Introduction).
+static double escape_norm2(const dqjo_params *p, const double z[8]) {
+  double s = 0.0;
+  const int ncomp = (p->norm == DQJO_NORM_REALPART) ? 4 : 8;
+  for (int k = 0; k < ncomp; ++k) s += z[k] * z[k];
+  return s;
+}
+
+// Section "Practical Considerations": iterate up to max_iter; a point that has not
+// passed the escape limit by then is inside. The test runs after every update
+// (z_0 itself is not tested) and is strict: ||z||^2 > R^2 escapes, a tie stays.
+int32_t dqjo_classify(const dqjo_params *p, const double z0[8], int32_t *m,
+                      double zfinal[8], double *norm2) {
+  const double R2 = p->escape_radius * p->escape_radius;
+  double z[8];
+  memcpy(z, z0, sizeof z);
+  double n2 = escape_norm2(p, z);
+  int32_t inside = 1;
+  int32_t n = 0;
+  for (n = 1; n <= p->max_iter; ++n) {
+    dq_step(z, p->c, z);
+    n2 = escape_norm2(p, z);
+    if (n2 > R2) {
+      inside = 0;
+      break;
+    }
+  }
+  if (inside) n = p->max_iter;
+  if (m) *m = n;
+  if (zfinal) memcpy(zfinal, z, sizeof z);
+  if (norm2) *norm2 = n2;
+  return inside;
+}
+
+void dqjo_classify_many(const dqjo_params *p, const double *pts, int64_t n,
+                        uint8_t *inside, int32_t *m, double *norm2, double *zfinal) {
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t mi;
+    double n2, zf[8];
+    const int32_t in = dqjo_classify(p, pts + 8 * i, &mi, zf, &n2);
+    if (inside) inside[i] = (uint8_t)in;
+    if (m) m[i] = mi;
+    if (norm2) norm2[i] = n2;
+    if (zfinal) memcpy(zfinal + 8 * i, zf, sizeof zf);
+  }
+}
+
+// Section "Dimension Reduction": a 3-flat through R^8, zeta_0 = O + X U + Y V + Z W.
+void dqjo_slice_map(const dqjo_params *p, const double x[3], double z0[8]) {
+  for (int k = 0; k < 8; ++k) {
+    z0[k] = p->slice_origin[k] + x[0] * p->slice_axes[0][k] + x[1] * p->slice_axes[1][k] +
+            x[2] * p->slice_axes[2][k];
+  }
+}
+
+static void normalize3(double v[3]) {
+  const double len = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  v[0] /= len;
+  v[1] /= len;
+  v[2] /= len;
+}
+
+static void cross3(const double a[3], const double b[3], double out[3]) {
+  double r[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+  memcpy(out, r, sizeof r);
+}
+
+// Pinhole camera (the paper leaves the camera to the renderer): forward f towards
+// the target, right r = f x up, true up u = r x f; vertical field of view; the ray
+// through the centre of pixel (i, j), row 0 at the top. Then the ray is clipped to
+// the axis-aligned box that bounds the fractal (the paper's bounding-volume cull,
+// section "Ray-Marching"), slab by slab.
+int32_t dqjo_ray(const dqjo_params *p, int32_t i, int32_t j, double o[3], double d[3],
+                 double *t0, double *t1) {
+  double f[3] = {p->target[0] - p->eye[0], p->target[1] - p->eye[1], p->target[2] - p->eye[2]};
+  normalize3(f);
+  double r[3];
+  cross3(f, p->up, r);
+  normalize3(r);
+  double u[3];
+  cross3(r, f, u);
+  const double pi = 3.14159265358979323846;
+  const double tan_half = tan(0.5 * p->fov_y_deg * pi / 180.0);
+  const double W = p->width, H = p->height;
+  const double sx = (2.0 * (i + 0.5) / W - 1.0) * tan_half * (W / H);
+  const double sy = (1.0 - 2.0 * (j + 0.5) / H) * tan_half;
+  for (int k = 0; k < 3; ++k) {
+    o[k] = p->eye[k];
+    d[k] = f[k] + sx * r[k] + sy * u[k];
+  }
+  normalize3(d);
+  double tn = 0.0, tf = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] == 0.0) {
+      if (o[k] < p->box_min[k] || o[k] > p->box_max[k]) return 0;
+      continue;
+    }
+    double ta = (p->box_min[k] - o[k]) / d[k];
+    double tb = (p->box_max[k] - o[k]) / d[k];
+    if (ta > tb) {
+      const double s = ta;
+      ta = tb;
+      tb = s;
+    }
+    if (ta > tn) tn = ta;
+    if (tb < tf) tf = tb;
+  }
+  if (tn > tf) return 0;
+  *t0 = tn;
+  *t1 = tf;
+  return 1;
+}
+
+static int32_t classify_world(const dqjo_params *p, const double x[3], int32_t *m) {
+  double z0[8];
+  dqjo_slice_map(p, x, z0);
+  return dqjo_classify(p, z0, m, nullptr, nullptr);
+}
+
+// Normals (section "Lighting/Illumination" samples neighbouring points with a small
+// delta). The sampled field is the smooth escape potential ln||z_m||^2 / 2^m, which
+// is continuous across escape-index changes (and equals 2 ln|x| exactly for c = 0).
+double dqjo_potential(const dqjo_params *p, const double x[3], int32_t *m) {
+  double z0[8], zf[8], n2;
+  int32_t mi;
+  dqjo_slice_map(p, x, z0);
+  dqjo_classify(p, z0, &mi, zf, &n2);
+  if (m) *m = mi;
+  const double v = n2 > 1e-30 ? n2 : 1e-30;
+  return log(v) * ldexp(1.0, -mi);
+}
+
+struct PixelResult {
+  uint8_t mask;
+  double depth, shade, normal[3];
+  int32_t first_hit;
+  uint64_t iters;
+};
+
+static PixelResult render_pixel(const dqjo_params *p, int32_t i, int32_t j) {
+  PixelResult res;
+  res.mask = 0;
+  res.depth = INFINITY;
+  res.shade = 0.0;
+  res.normal[0] = res.normal[1] = res.normal[2] = 0.0;
+  res.first_hit = -1;
+  res.iters = 0;
+
+  double o[3], d[3], t0, t1;
+  if (!dqjo_ray(p, i, j, o, d, &t0, &t1)) return res;
+
+  // Fixed-step march: S steps over [t0, t1], samples t_k = t0 + k dt, k = 0..S.
+  const int32_t S = p->march_steps;
+  const double dt = (t1 - t0) / S;
+  int32_t kstar = -1;
+  for (int32_t k = 0; k <= S; ++k) {
+    const double t = t0 + k * dt;
+    const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+    int32_t m;
+    const int32_t in = classify_world(p, x, &m);
+    res.iters += (uint64_t)m;
+    if (in) {
+      kstar = k;
+      break;
+    }
+  }
+  if (kstar < 0) return res;
+
+  // Bisection of the bracket [t_{k*-1}, t_{k*}]; the hit is the final midpoint.
+  // A hit on the first sample has no outside end to bracket: the hit is t0.
+  double thit;
+  if (kstar == 0) {
+    thit = t0;
+  } else {
+    double lo = t0 + (kstar - 1) * dt;
+    double hi = t0 + kstar * dt;
+    for (int32_t b = 0; b < p->bisect_steps; ++b) {
+      const double tm = 0.5 * (lo + hi);
+      const double x[3] = {o[0] + tm * d[0], o[1] + tm * d[1], o[2] + tm * d[2]};
+      int32_t m;
+      const int32_t in = classify_world(p, x, &m);
+      res.iters += (uint64_t)m;
+      if (in)
+        hi = tm;
+      else
+        lo = tm;
+    }
+    thit = 0.5 * (lo + hi);
+  }
+  const double ph[3] = {o[0] + thit * d[0], o[1] + thit * d[1], o[2] + thit * d[2]};
+
+  // Central differences of the potential along the world axes.
+  double g[3];
+  for (int a = 0; a < 3; ++a) {
+    double xp[3] = {ph[0], ph[1], ph[2]};
+    double xm[3] = {ph[0], ph[1], ph[2]};
+    xp[a] = ph[a] + p->normal_h;
+    xm[a] = ph[a] - p->normal_h;
+    int32_t mp, mm;
+    const double gp = dqjo_potential(p, xp, &mp);
+    const double gm = dqjo_potential(p, xm, &mm);
+    res.iters += (uint64_t)mp + (uint64_t)mm;
+    g[a] = gp - gm;
+  }
+  const double glen = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  double n[3];
+  if (glen > 0.0 && isfinite(glen)) {
+    n[0] = g[0] / glen;
+    n[1] = g[1] / glen;
+    n[2] = g[2] / glen;
+  } else {
+    n[0] = -d[0];
+    n[1] = -d[1];
+    n[2] = -d[2];
+  }
+
+  // Eq. phong, ambient and diffuse terms, one directional light, clamped to [0, 1].
+  double l[3] = {p->light_dir[0], p->light_dir[1], p->light_dir[2]};
+  normalize3(l);
+  double ndl = n[0] * l[0] + n[1] * l[1] + n[2] * l[2];
+  if (ndl < 0.0) ndl = 0.0;
+  double s = p->k_ambient + p->k_diffuse * ndl;
+  if (s < 0.0) s = 0.0;
+  if (s > 1.0) s = 1.0;
+
+  res.mask = 1;
+  res.depth = thit;
+  res.shade = s;
+  res.normal[0] = n[0];
+  res.normal[1] = n[1];
+  res.normal[2] = n[2];
+  res.first_hit = kstar;
+  return res;
+}
+
+uint64_t dqjo_render(const dqjo_params *p, const int64_t *pix, int64_t npix, uint8_t *mask,
+                     double *depth, double *shade, double *normal, int32_t *first_hit,
+                     uint64_t *iters, int32_t nthreads) {
+  const int64_t W = p->width;
+  const int64_t total = pix ? npix : W * (int64_t)p->height;
+  uint64_t sum = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : sum)
+  for (int64_t q = 0; q < total; ++q) {
+    const int64_t idx = pix ? pix[q] : q;
+    const PixelResult r = render_pixel(p, (int32_t)(idx % W), (int32_t)(idx / W));
+    if (mask) mask[q] = r.mask;
+    if (depth) depth[q] = r.depth;
+    if (shade) shade[q] = r.shade;
+    if (normal) {
+      normal[3 * q + 0] = r.normal[0];
+      normal[3 * q + 1] = r.normal[1];
+      normal[3 * q + 2] = r.normal[2];
+    }
+    if (first_hit) first_hit[q] = r.first_hit;
+    if (iters) iters[q] = r.iters;
+    sum += r.iters;
+  }
+  return sum;
+}
+
+int32_t dqjo_scan_ray(const dqjo_params *p, int32_t i, int32_t j, double ta, double tb,
+                      int32_t n, uint8_t *classes) {
+  double o[3], d[3], t0, t1;
+  dqjo_ray(p, i, j, o, d, &t0, &t1);
+  int32_t changes = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const double t = ta + (tb - ta) * k / (n - 1);
+    const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+    int32_t m;
+    classes[k] = (uint8_t)classify_world(p, x, &m);
+    if (k > 0 && classes[k] != classes[k - 1]) ++changes;
+  }
+  return changes;
+}
+
+uint32_t dqjo_params_size(void) { return (uint32_t)sizeof(dqjo_params); }
+
+}  // extern "C"

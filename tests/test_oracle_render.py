@@ -1,0 +1,194 @@
+"""Pins of the oracle's camera, march, bisection, normal and shading.
+
+* Camera: right-handed look-at conventions (camera on +z looking at the origin
+  with up +y sees +x on the right and +y at the top), the centre ray hits the
+  target, and the vertical field of view is the angle between the extreme rows.
+* Box clip: slab entry/exit on axis-aligned rays; an eye inside the box starts at 0.
+* c = 0: the inside set is the ball of radius rho = R^(2^-N) (closed form), so a
+  rendered frame has a closed form: hit iff the ray meets the ball, t_hit within
+  one bisection interval of the analytic entry point, normal radial, shade
+  k_a + k_d max(0, n.l).
+* March + bisection against a brute-force dense march at the bisection's
+  resolution, wherever the bracket holds a single crossing.
+* Work count: for c = 0 every update count has the closed form of the escape
+  index, so a frame's count is checked without the oracle's iteration code.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+
+def frame(c=None, W=32, H=32, N=12, S=64, B=8, **kw):
+    return workloads.Params(c=c if c is not None else [0.0] * 8, width=W, height=H,
+                            max_iter=N, march_steps=S, bisect_steps=B, **kw)
+
+
+def test_camera_right_handed_and_centre(oracle_mod):
+    p = frame(W=33, H=21, eye=[0.0, 0.0, 3.0])
+    hit, o, d, t0, t1 = oracle_mod.ray(p, 16, 10)
+    np.testing.assert_allclose(d, [0, 0, -1], atol=1e-15)
+    np.testing.assert_allclose(o, [0, 0, 3])
+    _, _, d_right, _, _ = oracle_mod.ray(p, 32, 10)
+    _, _, d_top, _, _ = oracle_mod.ray(p, 16, 0)
+    assert d_right[0] > 0.1 and abs(d_right[1]) < 1e-12
+    assert d_top[1] > 0.1 and abs(d_top[0]) < 1e-12
+    for (i, j) in [(0, 0), (32, 20), (5, 17)]:
+        _, _, d, _, _ = oracle_mod.ray(p, i, j)
+        assert abs(np.linalg.norm(d) - 1) < 1e-15
+
+
+def test_vertical_field_of_view(oracle_mod):
+    H = 4001
+    p = frame(W=3, H=H, eye=[0.0, 0.0, 3.0], fov_y_deg=60.0)
+    _, _, d_top, _, _ = oracle_mod.ray(p, 1, 0)
+    _, _, d_bot, _, _ = oracle_mod.ray(p, 1, H - 1)
+    ang = math.degrees(math.acos(np.dot(d_top, d_bot)))
+    # extreme row centres sit half a pixel inside the image edge
+    assert abs(ang - 60.0) < 0.03
+
+
+def test_box_clip(oracle_mod):
+    p = frame(W=33, H=33, eye=[0.0, 0.0, 3.0])
+    hit, o, d, t0, t1 = oracle_mod.ray(p, 16, 16)
+    assert hit and abs(t0 - 1.5) < 1e-15 and abs(t1 - 4.5) < 1e-15
+    inside = frame(W=33, H=33, eye=[0.5, 0.25, 1.0], target=[0.5, 0.25, 0.0])
+    hit, o, d, t0, t1 = oracle_mod.ray(inside, 16, 16)
+    assert hit and t0 == 0.0 and abs(t1 - 2.5) < 1e-15
+    away = frame(W=33, H=33, eye=[0.0, 0.0, 3.0], target=[0.0, 0.0, 6.0])
+    hit, *_ = oracle_mod.ray(away, 16, 16)
+    assert not hit
+
+
+def analytic_ball(o, d, rho):
+    b = np.dot(o, d)
+    disc = b * b - (np.dot(o, o) - rho * rho)
+    if disc < 0:
+        return None, 0.0
+    s = math.sqrt(disc)
+    return -b - s, 2 * s
+
+
+@pytest.mark.parametrize("N,S,B", [(12, 64, 8), (12, 128, 0), (24, 48, 10)])
+def test_c0_render_closed_form(oracle_mod, N, S, B):
+    W = H = 40
+    p = frame(W=W, H=H, N=N, S=S, B=B)
+    rho = 4.0 ** (2.0 ** -N)
+    r = oracle_mod.render(p)
+    l = np.array(p.light_dir) / np.linalg.norm(p.light_dir)
+    n_hit = 0
+    n_normal = 0
+    for j in range(H):
+        for i in range(W):
+            hit, o, d, t0, t1 = oracle_mod.ray(p, i, j)
+            dt = (t1 - t0) / S
+            tstar, chord = analytic_ball(o, d, rho)
+            if tstar is None:
+                assert r["mask"][j, i] == 0
+                assert math.isinf(r["depth"][j, i]) and r["shade"][j, i] == 0.0
+                continue
+            if chord < dt + 1e-9:
+                continue  # grazing: the chord can fall between two samples
+            assert r["mask"][j, i] == 1, (i, j)
+            n_hit += 1
+            assert abs(r["depth"][j, i] - tstar) <= dt * 2.0 ** -(B + 1) + 1e-12
+            ph = o + r["depth"][j, i] * d
+            nrm = ph / np.linalg.norm(ph)
+            # Inside radius r_clamp the potential sits on its 1e-30 floor (|x|^(2^(N+1))
+            # underflows it); the closed form holds where no stencil point is that deep.
+            r_clamp = math.exp(-math.log(1e30) / 2.0 ** (N + 1))
+            if np.linalg.norm(ph) - p.normal_h <= r_clamp:
+                continue
+            n_normal += 1
+            np.testing.assert_allclose(r["normal"][j, i], nrm, atol=1e-5)
+            shade = p.k_ambient + p.k_diffuse * max(0.0, float(np.dot(nrm, l)))
+            assert abs(r["shade"][j, i] - min(1.0, shade)) <= 1e-5
+            k = r["first_hit"][j, i]
+            # first inside sample is the first sample at or past the analytic entry
+            assert t0 + (k - 1) * dt < tstar + 1e-12 and t0 + k * dt >= tstar - 1e-12
+    assert n_hit > 200
+    if N == 12:
+        assert n_normal > 100
+
+
+def test_march_and_bisection_match_dense_scan(oracle_mod):
+    c = [-0.39054, -0.58679, 0, 0, 0.0, 0.5632, 0, 0.05]   # Fig. highres
+    S, B = 16, 4
+    p = frame(c=c, W=8, H=8, N=10, S=S, B=B)
+    r = oracle_mod.render(p)
+    checked = 0
+    for j in range(8):
+        for i in range(8):
+            hit, o, d, t0, t1 = oracle_mod.ray(p, i, j)
+            if not hit:
+                assert r["mask"][j, i] == 0
+                continue
+            dense, _ = oracle_mod.scan_ray(p, i, j, t0, t1, S * 2 ** B + 1)
+            coarse = dense[:: 2 ** B]
+            ins = np.nonzero(coarse)[0]
+            if len(ins) == 0:
+                assert r["mask"][j, i] == 0
+                continue
+            k = ins[0]
+            assert r["first_hit"][j, i] == k
+            if k == 0:
+                assert r["depth"][j, i] == t0
+                continue
+            seg = dense[(k - 1) * 2 ** B: k * 2 ** B + 1]
+            if np.count_nonzero(np.diff(seg.astype(int))) != 1:
+                continue  # several crossings inside the bracket: bisection may take any
+            q = np.nonzero(seg)[0][0]                      # first inside fine sample
+            dt_f = (t1 - t0) / (S * 2 ** B)
+            t_c = t0 + ((k - 1) * 2 ** B + q - 0.5) * dt_f  # midpoint of the fine bracket
+            assert abs(r["depth"][j, i] - t_c) <= 1e-9, (i, j)
+            checked += 1
+    assert checked >= 10
+
+
+def test_c0_iteration_count_closed_form(oracle_mod):
+    N, S, B = 12, 32, 6
+    W = H = 12
+    p = frame(W=W, H=H, N=N, S=S, B=B)
+    r = oracle_mod.render(p)
+
+    def esc(x):
+        rad = float(np.linalg.norm(x))
+        if rad <= 1.0:
+            return N
+        n = closed(rad)
+        return min(n, N)
+
+    def closed(rad):
+        xr = math.log(4.0) / math.log(rad)
+        return max(1, math.floor(math.log2(xr)) + 1)
+
+    for j in range(H):
+        for i in range(W):
+            hit, o, d, t0, t1 = oracle_mod.ray(p, i, j)
+            if not hit:
+                assert r["iters"][j, i] == 0
+                continue
+            dt = (t1 - t0) / S
+            total = 0
+            for k in range(S + 1):
+                x = o + (t0 + k * dt) * d
+                total += esc(x)
+                if closed_inside(x, N):
+                    break
+            if r["mask"][j, i] == 0:
+                assert r["iters"][j, i] == total
+            else:
+                # march part counted above; bisection adds B samples and the normal 6,
+                # each sample's count no more than N
+                extra = int(r["iters"][j, i]) - total
+                assert B + 6 <= extra <= (B + 6) * N
+
+
+def closed_inside(x, N):
+    rad = float(np.linalg.norm(x))
+    if rad <= 1.0:
+        return True
+    xr = math.log(4.0) / math.log(rad)
+    return max(1, math.floor(math.log2(xr)) + 1) > N
