@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the dual-quaternion Julia ray-march hot path on one MI355X.
+
+One step = one pass of the whole path (march, bisection, normal, shade, write) over
+the 1024x1024 workload: 3 seeded Julia constants, max_iter 24, 512 march steps,
+10 bisection steps, all three frames in one persistent launch replayed from a HIP
+graph. Inputs (parameters) are resident on the device before timing starts.
+
+value = Julia iterations per second = I_alg / t, where I_alg is the number of
+dual-quaternion updates the method runs for the three frames as counted by the
+FP64 oracle (tests/golden/ialg_plain_1024.json), and t the wall time per step.
+Each update is priced at 52 FP32 flops (37 for z^2 + c, 15 for the 8-square norm)
+for the roofline against the FP32 vector peak.
+
+Prints ONE JSON line. ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Julia iters/sec & % FP32 VALU peak; p50/p99 frame latency served vs plain"
+FLOPS_PER_UPDATE = 52
+FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector (packed) peak
+FP32_UNPACKED_TFLOPS = 78.6       # one FP32 FMA per lane per clock (no packed FP32)
+
+
+def cpu_threads():
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(ps, target_s):
+    """The FP64 oracle on a bounded random sample of the same frames' pixels."""
+    import numpy as np
+    import oracle
+    nthreads = cpu_threads()
+    rng = np.random.default_rng(12345)
+    # calibrate on a small sample, then size the sample to about target_s seconds
+    pilot = [np.sort(rng.choice(p.width * p.height, 600, replace=False)) for p in ps]
+    t = time.perf_counter()
+    it = sum(oracle.render(p, pixels=pix, nthreads=nthreads)["total_iters"] for p, pix in zip(ps, pilot))
+    rate_px = 600 * len(ps) / max(time.perf_counter() - t, 1e-6)
+    per_frame = int(min(max(target_s * rate_px / len(ps), 1000), ps[0].width * ps[0].height))
+    sample = [np.sort(rng.choice(p.width * p.height, per_frame, replace=False)) for p in ps]
+    t = time.perf_counter()
+    it = sum(oracle.render(p, pixels=pix, nthreads=nthreads)["total_iters"] for p, pix in zip(ps, sample))
+    dt = time.perf_counter() - t
+    return {"value": it / dt, "unit": "Julia iters/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{per_frame} uniformly sampled pixels of each of the {len(ps)} frames "
+                      f"({per_frame * len(ps)} rays, {it} updates, {dt:.1f} s, FP64)",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernel", choices=["refill", "direct"], default="refill")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(every pixel, frame and request is independent: see the sharding design)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2303_14827_amd as dqj
+    import workloads
+
+    ps = workloads.plain_1024()
+    golden_path = os.path.join(ROOT, "tests", "golden", "ialg_plain_1024.json")
+    with open(golden_path) as f:
+        golden = json.load(f)
+    for fr, p in zip(golden["frames"], ps):
+        assert [round(x, 7) for x in fr["c"]] == [round(x, 7) for x in p.c], "golden/c mismatch"
+    ialg = int(golden["total_iters"])
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    info = dqj.device_info(0)
+    stream = torch.cuda.current_stream()
+    outs = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
+
+    if args.kernel == "refill":
+        plan = dqj.BatchPlan(ps, outs)
+
+        def step():
+            plan.launch(stream)
+    else:
+        sched = dqj.make_schedule(kernel=dqj.KERNEL_DIRECT)
+
+        def step():
+            for p, o in zip(ps, outs):
+                dqj.render(p, out=o, stream=stream, schedule=sched)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for o in outs:
+        o["iters"].zero_()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    exec_iters = sum(int(o["iters"].item()) for o in outs) / args.steps
+    hits = [int(o["mask"].sum().item()) for o in outs]
+
+    value = ialg / (ms_per_step * 1e-3)
+    achieved_tf = FLOPS_PER_UPDATE * ialg / (ev_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Julia iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain_1024: 3 seeded c (seeds 0,1,2; real comps U[-0.6,0.6], "
+                               "dual U[-0.5,0.5]), 1024x1024, max_iter 24, escape radius 4, "
+                               "512 march steps, 10 bisection steps, one graph-replayed "
+                               "persistent launch per step",
+                   "frames": 3, "width": 1024, "height": 1024, "max_iter": 24,
+                   "march_steps": 512, "bisect_steps": 10, "kernel": args.kernel},
+        "pct_fp32_peak": 100.0 * achieved_tf / FP32_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / FP32_PEAK_TFLOPS,
+                     "traffic": None,
+                     "kernel": "render_refill_kernel" if args.kernel == "refill" else
+                               "render_direct_kernel",
+                     "kernel_ms_per_launch": ev_ms,
+                     "flops_per_launch": FLOPS_PER_UPDATE * ialg,
+                     "frac_of_unpacked_fp32": achieved_tf / FP32_UNPACKED_TFLOPS},
+        "ialg_per_step": ialg,
+        "ialg_source": "FP64 oracle, tests/golden/ialg_plain_1024.json",
+        "gpu_counted_iters_per_step": exec_iters,
+        "hits_per_frame": hits,
+        "device": {"arch": info["arch"], "cus": info["compute_units"],
+                   "clock_mhz": info["clock_khz"] / 1000.0},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
+    if args.kernel == "refill":
+        plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,14 +118,25 @@ dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *
 dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
                             void *hip_stream);
 
+/* Kernel choice for FP32 renders. REFILL: persistent waves whose lanes take the
+ * next sample or ray as soon as theirs retires. DIRECT: one thread per pixel, the
+ * method's steps in order, no refill (the simple yardstick). */
+enum { DQJ_KERNEL_AUTO = 0, DQJ_KERNEL_REFILL = 1, DQJ_KERNEL_DIRECT = 2 };
+
 /* Work schedule of the persistent kernels (chosen by dqj_autotune, or by hand).
- * Any field 0 = library default. */
+ * Any field 0 = library default. A schedule changes speed only: every schedule
+ * gives bit-identical images. */
 typedef struct dqj_schedule {
-  uint32_t struct_size;
+  uint32_t struct_size;        /* = sizeof(dqj_schedule) */
+  int32_t kernel;              /* DQJ_KERNEL_* */
   int32_t tile_w, tile_h;      /* pixels per tile handed to one wave (tile_w*tile_h <= 4096) */
   int32_t waves_per_block;     /* 1..16 (block = 64 * waves_per_block threads) */
-  int32_t blocks_per_cu;       /* persistent grid = CUs * blocks_per_cu */
+  int32_t blocks_per_cu;       /* persistent grid = CUs * blocks_per_cu, 1..32 */
 } dqj_schedule;
+
+/* dqj_render with an explicit schedule (NULL = default). */
+dqj_status dqj_render_scheduled(const dqj_params *params, const dqj_frame_out *out,
+                                const dqj_schedule *sched, void *hip_stream);
 
 /* A batch captured once into a HIP graph and replayed: the parameter table stays
  * resident in device memory, each replay is one queue reset plus one persistent

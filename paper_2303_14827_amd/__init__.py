@@ -1,0 +1,294 @@
+"""Python binding of libdqj (dual-quaternion Julia ray marching on MI355X / gfx950).
+
+Argument marshalling only: every step of the render runs in the library's HIP
+kernels. PyTorch provides device memory and the current HIP stream. The library
+is built in-tree (``python -m paper_2303_14827_amd.build``); importing this module
+does not load it, the first call does, and fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdqj.so")
+
+OK, PENDING = 0, 1
+E_INVALID, E_NOMEM, E_BUDGET, E_QUEUE_FULL, E_DEVICE = -1, -2, -3, -4, -5
+E_TIMEOUT, E_CANCELLED, E_UNSUPPORTED, E_STATE = -6, -7, -8, -9
+
+NORM_EUCLID8, NORM_REALPART = 0, 1
+PREC_FP32, PREC_SPLIT, PREC_FP64 = 0, 1, 2
+KERNEL_AUTO, KERNEL_REFILL, KERNEL_DIRECT = 0, 1, 2
+FLAG_BOX, FLAG_HIT, FLAG_FP64, FLAG_FALLBACK = 1, 2, 4, 8
+
+
+class DQJError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+class dqj_params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("c", C.c_double * 8),
+        ("slice_origin", C.c_double * 8),
+        ("slice_axes", (C.c_double * 8) * 3),
+        ("box_min", C.c_double * 3),
+        ("box_max", C.c_double * 3),
+        ("eye", C.c_double * 3),
+        ("target", C.c_double * 3),
+        ("up", C.c_double * 3),
+        ("fov_y_deg", C.c_double),
+        ("width", C.c_int32),
+        ("height", C.c_int32),
+        ("max_iter", C.c_int32),
+        ("march_steps", C.c_int32),
+        ("bisect_steps", C.c_int32),
+        ("escape_radius", C.c_double),
+        ("norm", C.c_int32),
+        ("precision", C.c_int32),
+        ("fp64_window", C.c_int32),
+        ("normal_h", C.c_double),
+        ("light_dir", C.c_double * 3),
+        ("k_ambient", C.c_double),
+        ("k_diffuse", C.c_double),
+    ]
+
+
+class dqj_frame_out(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("mask", C.c_void_p),
+        ("depth", C.c_void_p),
+        ("shade", C.c_void_p),
+        ("image8", C.c_void_p),
+        ("normal", C.c_void_p),
+        ("first_hit", C.c_void_p),
+        ("flags", C.c_void_p),
+        ("iters", C.c_void_p),
+    ]
+
+
+class dqj_schedule(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("kernel", C.c_int32),
+        ("tile_w", C.c_int32),
+        ("tile_h", C.c_int32),
+        ("waves_per_block", C.c_int32),
+        ("blocks_per_cu", C.c_int32),
+    ]
+
+
+class dqj_device_info(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("arch", C.c_char * 64),
+        ("compute_units", C.c_int32),
+        ("clock_khz", C.c_int32),
+        ("memory_clock_khz", C.c_int32),
+        ("total_mem_bytes", C.c_uint64),
+        ("fp32_vector_peak_tflops", C.c_double),
+        ("fp32_unpacked_peak_tflops", C.c_double),
+    ]
+
+
+_lib = None
+
+# symbol -> (restype, argtypes)
+_SIGS = {
+    "dqj_render": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out), C.c_void_p]),
+    "dqj_render_scheduled": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out),
+                                         C.POINTER(dqj_schedule), C.c_void_p]),
+    "dqj_render_batch": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out), C.c_int32,
+                                     C.c_void_p]),
+    "dqj_batch_plan_create": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out),
+                                          C.c_int32, C.POINTER(dqj_schedule), C.c_void_p,
+                                          C.POINTER(C.c_void_p)]),
+    "dqj_batch_plan_launch": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "dqj_batch_plan_destroy": (C.c_int32, [C.c_void_p]),
+    "dqj_classify_points": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(dqj_params),
+                                        C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dqj_device_info_get": (C.c_int32, [C.c_int32, C.POINTER(dqj_device_info)]),
+    "dqj_last_error": (C.c_char_p, []),
+    "dqj_status_str": (C.c_char_p, [C.c_int32]),
+}
+
+
+def lib():
+    """Load libdqj.so. Raises if it has not been built: there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2303_14827_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    if _lib is None:
+        return str(s)
+    return _lib.dqj_status_str(int(s)).decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise DQJError(status, lib().dqj_last_error().decode())
+
+
+def make_params(p) -> dqj_params:
+    """Fill a dqj_params from a ``workloads.Params``-like object."""
+    s = dqj_params()
+    s.struct_size = C.sizeof(dqj_params)
+    s.c[:] = [float(x) for x in p.c]
+    s.slice_origin[:] = [float(x) for x in p.slice_origin]
+    for a in range(3):
+        s.slice_axes[a][:] = [float(x) for x in p.slice_axes[a]]
+    s.box_min[:] = list(p.box_min)
+    s.box_max[:] = list(p.box_max)
+    s.eye[:] = list(p.eye)
+    s.target[:] = list(p.target)
+    s.up[:] = list(p.up)
+    s.fov_y_deg = p.fov_y_deg
+    s.width, s.height = p.width, p.height
+    s.max_iter, s.march_steps, s.bisect_steps = p.max_iter, p.march_steps, p.bisect_steps
+    s.escape_radius = p.escape_radius
+    s.norm, s.precision, s.fp64_window = p.norm, p.precision, p.fp64_window
+    s.normal_h = p.normal_h
+    s.light_dir[:] = list(p.light_dir)
+    s.k_ambient, s.k_diffuse = p.k_ambient, p.k_diffuse
+    return s
+
+
+def make_schedule(kernel=0, tile_w=0, tile_h=0, waves_per_block=0, blocks_per_cu=0) -> dqj_schedule:
+    s = dqj_schedule()
+    s.struct_size = C.sizeof(dqj_schedule)
+    s.kernel, s.tile_w, s.tile_h = kernel, tile_w, tile_h
+    s.waves_per_block, s.blocks_per_cu = waves_per_block, blocks_per_cu
+    return s
+
+
+def alloc_outputs(width: int, height: int, device="cuda", extras: bool = True):
+    """Device output tensors for one frame (torch, caller-owned)."""
+    import torch
+    o = {
+        "mask": torch.empty((height, width), dtype=torch.uint8, device=device),
+        "depth": torch.empty((height, width), dtype=torch.float32, device=device),
+        "shade": torch.empty((height, width), dtype=torch.float32, device=device),
+        "iters": torch.zeros((1,), dtype=torch.int64, device=device),
+    }
+    if extras:
+        o["image8"] = torch.empty((height, width), dtype=torch.uint8, device=device)
+        o["normal"] = torch.empty((height, width, 3), dtype=torch.float32, device=device)
+        o["first_hit"] = torch.empty((height, width), dtype=torch.int32, device=device)
+        o["flags"] = torch.empty((height, width), dtype=torch.uint8, device=device)
+    return o
+
+
+def make_frame_out(o: Dict) -> dqj_frame_out:
+    f = dqj_frame_out()
+    f.struct_size = C.sizeof(dqj_frame_out)
+    for name in ("mask", "depth", "shade", "image8", "normal", "first_hit", "flags", "iters"):
+        t = o.get(name)
+        setattr(f, name, t.data_ptr() if t is not None else None)
+    return f
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def render(p, out: Optional[Dict] = None, stream=None, schedule: Optional[dqj_schedule] = None,
+           extras: bool = True) -> Dict:
+    """Enqueue one frame on the stream; returns the output tensor dict."""
+    if out is None:
+        out = alloc_outputs(p.width, p.height, extras=extras)
+    sp = make_params(p)
+    fo = make_frame_out(out)
+    if schedule is None:
+        _check(lib().dqj_render(C.byref(sp), C.byref(fo), _stream(stream)))
+    else:
+        _check(lib().dqj_render_scheduled(C.byref(sp), C.byref(fo), C.byref(schedule),
+                                          _stream(stream)))
+    return out
+
+
+def render_batch(ps: Sequence, outs: Optional[List[Dict]] = None, stream=None,
+                 extras: bool = False) -> List[Dict]:
+    """Enqueue n frames as one persistent launch; returns the output dicts."""
+    n = len(ps)
+    if outs is None:
+        outs = [alloc_outputs(p.width, p.height, extras=extras) for p in ps]
+    arr_p = (dqj_params * n)(*[make_params(p) for p in ps])
+    arr_o = (dqj_frame_out * n)(*[make_frame_out(o) for o in outs])
+    _check(lib().dqj_render_batch(arr_p, arr_o, n, _stream(stream)))
+    return outs
+
+
+class BatchPlan:
+    """A batch captured into a HIP graph once and replayed with launch()."""
+
+    def __init__(self, ps: Sequence, outs: List[Dict], schedule: Optional[dqj_schedule] = None,
+                 stream=None):
+        n = len(ps)
+        self.outs = outs
+        arr_p = (dqj_params * n)(*[make_params(p) for p in ps])
+        arr_o = (dqj_frame_out * n)(*[make_frame_out(o) for o in outs])
+        h = C.c_void_p()
+        _check(lib().dqj_batch_plan_create(arr_p, arr_o, n,
+                                           C.byref(schedule) if schedule is not None else None,
+                                           _stream(stream), C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().dqj_batch_plan_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            _check(lib().dqj_batch_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def classify_points(pts, p, precision: int = PREC_FP32, stream=None):
+    """Classify device points (n x 8, float32 or float64). Returns (escape_iter, final_norm2)."""
+    import torch
+    n = pts.shape[0]
+    esc = torch.empty((n,), dtype=torch.int32, device=pts.device)
+    n2 = torch.empty((n,), dtype=torch.float32, device=pts.device)
+    sp = make_params(p)
+    _check(lib().dqj_classify_points(C.c_void_p(pts.data_ptr()), n, precision, C.byref(sp),
+                                     C.c_void_p(esc.data_ptr()), C.c_void_p(n2.data_ptr()),
+                                     _stream(stream)))
+    return esc, n2
+
+
+def device_info(device: int = 0) -> Dict:
+    d = dqj_device_info()
+    d.struct_size = C.sizeof(dqj_device_info)
+    _check(lib().dqj_device_info_get(device, C.byref(d)))
+    return {"arch": d.arch.decode(), "compute_units": d.compute_units, "clock_khz": d.clock_khz,
+            "memory_clock_khz": d.memory_clock_khz, "total_mem_bytes": d.total_mem_bytes,
+            "fp32_vector_peak_tflops": d.fp32_vector_peak_tflops,
+            "fp32_unpacked_peak_tflops": d.fp32_unpacked_peak_tflops}
+
+
+def exported_symbols() -> List[str]:
+    return sorted(_SIGS)

@@ -1,0 +1,201 @@
+// dq_device.h -- device building blocks of the ray-march path (library-internal).
+//
+// The dual-quaternion square uses the cross-product-free form of the product
+// rule: for zeta = a + e b,
+//   a^2      = (a0^2 - |a_v|^2, 2 a0 a_v)                         (Eq. quatsq)
+//   a b + b a = (2 (a0 b0 - a_v . b_v), 2 (a0 b_v + b0 a_v))       (the cross
+//   products of the two Hamilton products cancel)
+// so one update zeta <- zeta^2 + c (Eq. dqjulia2) is 37 flops and the 8-square
+// escape norm 15 more.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "dqj.h"
+#include "kparams.h"
+
+namespace dqj {
+
+// 8-component state held in registers.
+template <typename T>
+struct DQ {
+  T a0, a1, a2, a3, b0, b1, b2, b3;
+};
+
+// One update z <- z^2 + c given s = |a_v|^2 of the current z. Leaves z at z',
+// s at |a'_v|^2 (which the next update needs, so the escape norm reuses it) and
+// returns ||z'||^2 under NORM (0: all 8 squares, 1: the real quaternion's 4).
+// 26 VALU operations, 13 of them fused multiply-adds.
+template <int NORM, typename T>
+__device__ __forceinline__ T dq_update(DQ<T> &z, T &s, const T *c) {
+  const T ta = z.a0 + z.a0;
+  const T tb = z.b0 + z.b0;
+  const T dot = fma(z.a3, z.b3, fma(z.a2, z.b2, z.a1 * z.b1));
+  DQ<T> r;
+  r.a0 = fma(z.a0, z.a0, c[0] - s);
+  r.a1 = fma(ta, z.a1, c[1]);
+  r.a2 = fma(ta, z.a2, c[2]);
+  r.a3 = fma(ta, z.a3, c[3]);
+  r.b0 = fma(ta, z.b0, fma(T(-2), dot, c[4]));
+  r.b1 = fma(ta, z.b1, fma(tb, z.a1, c[5]));
+  r.b2 = fma(ta, z.b2, fma(tb, z.a2, c[6]));
+  r.b3 = fma(ta, z.b3, fma(tb, z.a3, c[7]));
+  const T s2 = fma(r.a3, r.a3, fma(r.a2, r.a2, r.a1 * r.a1));
+  T n2 = fma(r.a0, r.a0, s2);
+  if (NORM == 0) n2 = fma(r.b3, r.b3, fma(r.b2, r.b2, fma(r.b1, r.b1, fma(r.b0, r.b0, n2))));
+  z = r;
+  s = s2;
+  return n2;
+}
+
+template <typename T>
+__device__ __forceinline__ T vec_s(const DQ<T> &z) {
+  return fma(z.a3, z.a3, fma(z.a2, z.a2, z.a1 * z.a1));
+}
+
+// Iterate up to N updates, testing after each (strict > R2). Returns the escape
+// index m in 1..N, or 0 if the point stayed inside; z is left at z_m (z_N when
+// inside) and *n2 at its norm.
+template <int NORM, typename T>
+__device__ __forceinline__ int dq_classify(DQ<T> &z, const T *c, int N, T R2, T *n2) {
+  T s = vec_s(z);
+  T nn = T(0);
+  for (int n = 1; n <= N; ++n) {
+    nn = dq_update<NORM>(z, s, c);
+    if (nn > R2) {
+      *n2 = nn;
+      return n;
+    }
+  }
+  *n2 = nn;
+  return 0;
+}
+
+// World point -> R^8 through the slice zeta_0 = O + X U + Y V + Z W.
+template <typename T>
+__device__ __forceinline__ DQ<T> slice_map(const KParams &P, T x, T y, T z) {
+  T v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = T(P.so[k]) + x * T(P.su[k]) + y * T(P.sv[k]) + z * T(P.sw[k]);
+  return DQ<T>{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+}
+
+// Camera ray through the centre of pixel (i, j), row 0 at the top.
+__device__ __forceinline__ void pixel_dir(const KParams &P, int i, int j, float d[3]) {
+  const float sx = fmaf((float)(2 * i + 1), P.inv_w, -1.0f) * P.sx_scale;
+  const float sy = fmaf(-(float)(2 * j + 1), P.inv_h, 1.0f) * P.sy_scale;
+  float v[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = P.fwd[k] + sx * P.right[k] + sy * P.up[k];
+  const float inv = 1.0f / sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  d[0] = v[0] * inv;
+  d[1] = v[1] * inv;
+  d[2] = v[2] * inv;
+}
+
+// Slab clip of the ray eye + t d against the box; t0 >= 0. False if it misses.
+template <typename T>
+__device__ __forceinline__ bool clip_box(const KParams &P, const T d[3], T &t0, T &t1) {
+  T tn = T(0), tf = T(INFINITY);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T o = T(P.eye[k]);
+    if (d[k] == T(0)) {
+      if (o < T(P.bmin[k]) || o > T(P.bmax[k])) return false;
+      continue;
+    }
+    T ta = (T(P.bmin[k]) - o) / d[k];
+    T tb = (T(P.bmax[k]) - o) / d[k];
+    if (ta > tb) {
+      const T s = ta;
+      ta = tb;
+      tb = s;
+    }
+    tn = ta > tn ? ta : tn;
+    tf = tb < tf ? tb : tf;
+  }
+  if (tn > tf) return false;
+  t0 = tn;
+  t1 = tf;
+  return true;
+}
+
+// Smooth escape potential ln(max(||z_m||^2, 1e-30)) * 2^-m (m = N when inside).
+template <typename T>
+__device__ __forceinline__ T potential(T n2, int m) {
+  const T v = n2 > T(1e-30) ? n2 : T(1e-30);
+  return log(v) * ldexp(T(1), -m);
+}
+
+// Outputs of one pixel.
+struct PixelOut {
+  float depth, shade, nx, ny, nz;
+  int32_t first_hit;
+  uint8_t mask, flags;
+};
+
+__device__ __forceinline__ void write_pixel(const KOut &o, int64_t idx, const PixelOut &r) {
+  o.mask[idx] = r.mask;
+  o.depth[idx] = r.depth;
+  o.shade[idx] = r.shade;
+  if (o.image8) o.image8[idx] = (uint8_t)floorf(fmaf(255.0f, r.shade, 0.5f));
+  if (o.normal) {
+    o.normal[3 * idx + 0] = r.nx;
+    o.normal[3 * idx + 1] = r.ny;
+    o.normal[3 * idx + 2] = r.nz;
+  }
+  if (o.first_hit) o.first_hit[idx] = r.first_hit;
+  if (o.flags) o.flags[idx] = r.flags;
+}
+
+__device__ __forceinline__ PixelOut miss_pixel(uint8_t flags) {
+  PixelOut r;
+  r.depth = INFINITY;
+  r.shade = 0.0f;
+  r.nx = r.ny = r.nz = 0.0f;
+  r.first_hit = -1;
+  r.mask = 0;
+  r.flags = flags;
+  return r;
+}
+
+// Unit normal from the central-difference gradient g; -d when g is zero or not
+// finite. Shade = clamp(k_a + k_d max(0, n.l), 0, 1).
+template <typename T>
+__device__ __forceinline__ void finish_hit(const KParams &P, const T g[3], const T d[3], T thit,
+                                           int kstar, uint8_t flags, PixelOut &r) {
+  const T gl = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  T n[3];
+  if (gl > T(0) && isfinite(gl)) {
+    n[0] = g[0] / gl;
+    n[1] = g[1] / gl;
+    n[2] = g[2] / gl;
+  } else {
+    n[0] = -d[0];
+    n[1] = -d[1];
+    n[2] = -d[2];
+    flags |= DQJ_FLAG_FALLBACK;
+  }
+  T ndl = n[0] * T(P.light[0]) + n[1] * T(P.light[1]) + n[2] * T(P.light[2]);
+  ndl = ndl > T(0) ? ndl : T(0);
+  T s = T(P.ka) + T(P.kd) * ndl;
+  s = s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
+  r.depth = (float)thit;
+  r.shade = (float)s;
+  r.nx = (float)n[0];
+  r.ny = (float)n[1];
+  r.nz = (float)n[2];
+  r.first_hit = kstar;
+  r.mask = 1;
+  r.flags = flags;
+}
+
+// Wave-wide sum, then one 64-bit atomic per wave.
+__device__ __forceinline__ void wave_add_u64(unsigned long long *dst, unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+}  // namespace dqj

@@ -1,0 +1,63 @@
+// kparams.h -- the FP32 record one frame's kernels read (library-internal).
+//
+// The host turns a dqj_params (FP64) into this record: it builds the camera basis
+// and all derived constants in FP64 and rounds each once to FP32. Kernels of a
+// single frame take it by value (kernel arguments, read through the scalar
+// cache); batched and served kernels read it from a device-resident table.
+#pragma once
+#include <stdint.h>
+
+namespace dqj {
+
+struct alignas(16) KParams {
+  float c[8];            // Julia constant [r0..r3 | d0..d3]
+  float so[8];           // slice origin O
+  float su[8], sv[8], sw[8];   // slice axes U, V, W
+  float eye[3];
+  float R2;              // escape radius squared
+  float fwd[3];
+  float h;               // normal step
+  float right[3];
+  float sx_scale;        // tan(fov_y / 2) * W / H
+  float up[3];
+  float sy_scale;        // tan(fov_y / 2)
+  float bmin[3];
+  float inv_w;
+  float bmax[3];
+  float inv_h;
+  float light[3];        // unit vector towards the light
+  float ka;
+  float kd;
+  int32_t W, H, N;       // image size, max_iter
+  int32_t S, B;          // march steps, bisection steps
+  int32_t norm;          // 0: 8 squares, 1: real part only
+  int32_t axis_slice;    // 1 if O = 0 and U, V, W = e0, e1, e2 (zeta_0 = (X, Y, Z, 0 | 0))
+  int32_t fp64_window;   // split precision verify window
+  int32_t pad[2];
+};
+static_assert(sizeof(KParams) % 16 == 0, "KParams must be 16-byte sized");
+
+// What one frame writes (device pointers; optional ones may be null).
+struct KOut {
+  uint8_t *mask;
+  float *depth;
+  float *shade;
+  uint8_t *image8;
+  float *normal;
+  int32_t *first_hit;
+  uint8_t *flags;
+  unsigned long long *iters;
+};
+
+// One frame of a (possibly single-frame) persistent launch: its parameters, its
+// outputs, and where its tiles sit in the launch's global tile sequence.
+struct alignas(16) FrameDesc {
+  KParams P;
+  KOut out;
+  uint32_t tile_begin;   // first global tile index of this frame
+  uint32_t tiles_x;      // tiles per image row
+  uint32_t ntiles;       // tiles of this frame
+  uint32_t pad;
+};
+
+}  // namespace dqj

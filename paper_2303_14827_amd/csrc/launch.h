@@ -1,0 +1,25 @@
+// launch.h -- host-side launchers of the library's kernels (library-internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kparams.h"
+
+namespace dqj {
+
+// FP64 iteration constants for FP64 kernels (the caller's values, not FP32-rounded).
+struct KIter64 {
+  double c[8];
+  double R2;
+  int32_t N, norm;
+};
+
+// Straightforward FP32 render: one thread per pixel, no lane refill.
+hipError_t launch_render_direct(const KParams &P, const KOut &out, hipStream_t s);
+
+// Classify n points of R^8 (row-major n x 8) in FP32 / FP64.
+hipError_t launch_classify_f32(const float *pts, int n, const KParams &P, int32_t *esc,
+                               float *n2, hipStream_t s);
+hipError_t launch_classify_f64(const double *pts, int n, const KIter64 &P, int32_t *esc,
+                               float *n2, hipStream_t s);
+
+}  // namespace dqj

@@ -1,0 +1,26 @@
+// refill.h -- launchers of the persistent refill kernels (library-internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kparams.h"
+#include "runtime_internal.h"
+
+namespace dqj {
+
+// One frame; counter is a device word private to the stream (reset by the launch).
+hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
+                                hipStream_t stream);
+
+// n frames from a device-resident table; all frames share norm; all_axis is true only
+// if every frame uses the identity slice.
+hipError_t launch_render_refill_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
+                                      int norm, bool all_axis, uint32_t *counter, const Sched &s,
+                                      int cus, hipStream_t stream);
+
+// Fill the tile geometry of a frame descriptor (tile_begin must be set by the caller).
+inline void set_tiles(FrameDesc &f, int tw, int th) {
+  f.tiles_x = (uint32_t)((f.P.W + tw - 1) / tw);
+  f.ntiles = f.tiles_x * (uint32_t)((f.P.H + th - 1) / th);
+}
+
+}  // namespace dqj

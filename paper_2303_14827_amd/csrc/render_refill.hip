@@ -1,0 +1,364 @@
+// render_refill.hip -- persistent FP32 ray marcher with per-lane work refill.
+//
+// Each lane owns one ray and walks the method as a small state machine:
+//   MARCH  : classify sample k of the fixed-step march (section "Ray-Marching");
+//            outside -> sample k+1, inside -> BISECT (or NORMAL when k = 0 or B = 0);
+//   BISECT : classify the bracket midpoint B times;
+//   NORMAL : classify the 6 central-difference points and accumulate the gradient
+//            of the escape potential (section "Lighting/Illumination"), then shade
+//            (Eq. phong, ambient + diffuse) and write the pixel.
+// Every trip of the main loop applies ONE update z <- z^2 + c (Eq. dqjulia2) to
+// every busy lane; a lane whose point retires (escaped, or max_iter reached) takes
+// its next point at once, and a lane whose ray is finished takes the next ray of
+// its wave's tile. So no lane waits for the slowest ray of its wave: the cost of
+// divergence is the transition code, not idle lanes.
+//
+// Waves are persistent and take tiles (tile_w x tile_h pixels) from one global
+// atomic counter over all frames of the launch. A wave finishes every ray of a
+// frame before it starts a tile of another frame, so the Julia constant and the
+// camera stay wave-uniform (scalar registers). Results do not depend on which
+// lane or wave computes a pixel: images are bit-identical under any schedule.
+#include "dq_device.h"
+#include "launch.h"
+#include "refill.h"
+
+#include <cstring>
+
+namespace dqj {
+
+namespace {
+
+enum { PH_IDLE = 0, PH_MARCH = 1, PH_BISECT = 2, PH_NORMAL = 3 };
+
+__device__ __forceinline__ int rank_in(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Frame of a global tile index (frames are in tile order).
+__device__ __forceinline__ int find_frame(const FrameDesc *table, int nframes, uint32_t tile) {
+  int lo = 0, hi = nframes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].tile_begin <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// zeta_0 for a world point and |a_v|^2 of it.
+template <bool AXIS>
+__device__ __forceinline__ void start_point(const KParams &P, float x, float y, float zc,
+                                            DQ<float> &z, float &s) {
+  if (AXIS) {
+    z = DQ<float>{x, y, zc, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    s = fmaf(zc, zc, y * y);
+  } else {
+    z = slice_map<float>(P, x, y, zc);
+    s = vec_s(z);
+  }
+}
+
+}  // namespace
+
+template <int NORM, bool AXIS, bool BATCH>
+__global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
+                                                             const FrameDesc *__restrict__ table,
+                                                             int nframes, uint32_t total_tiles,
+                                                             uint32_t *__restrict__ counter,
+                                                             int TW, int TH) {
+  const int lane = lane_id();
+  const int tile_rays = TW * TH;
+
+  // ---- wave-uniform state
+  const FrameDesc *F = BATCH ? nullptr : &single;
+  int frame = -1;
+  uint32_t tile_local = 0;      // tile index within the frame
+  int next_r = 0;               // next ray of the tile to hand out
+  bool have_tile = false, pending = false, exhausted = false;
+  uint32_t pend_tile = 0;
+  float c[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) c[q] = 0.0f;
+  float R2 = 0.0f, c3sq = 0.0f, cdsq = 0.0f, Sf = 0.0f;
+  int N = 1;
+  bool closed_first = false;   // first march update in closed form (identity slice, N > 1)
+
+  // ---- per-lane state
+  int phase = PH_IDLE;
+  DQ<float> z{0, 0, 0, 0, 0, 0, 0, 0};
+  float s = 0.0f;
+  int n = 0;              // updates applied to the current point
+  int pix = 0;
+  float dx = 0, dy = 0, dz = 0, t0 = 0, dt = 0;
+  float k = 0.0f;         // march sample index (exact in FP32 up to 2^24)
+  int b = 0, sidx = 0, kstar = -1;
+  float lo = 0, hi = 0, thit = 0, gx = 0, gy = 0, gz = 0;
+  uint32_t it_lane = 0;
+
+  for (;;) {
+    // ---- one update on every lane (idle lanes compute and discard)
+    const float n2 = dq_update<NORM>(z, s, c);
+    ++n;
+    const bool esc = n2 > R2;
+    const bool done = phase != PH_IDLE && (esc || n >= N);
+
+    if (done) {
+      // Fast path: an outside march sample with more samples to go starts the next
+      // sample here. With the identity slice its first update is taken in closed form
+      // (zeta_0 = (x, y, z, 0 | 0) gives z_1 = (x^2 - y^2 - z^2 + c0, 2xy + c1, 2xz + c2,
+      // c3 | c_d)); a sample that escapes on that update is parked on a state that
+      // escapes on the next one, so it retires with escape index 1.
+      const bool fast = esc && phase == PH_MARCH && k < Sf;
+      if (fast) {
+        it_lane += (uint32_t)n;
+        k += 1.0f;
+        const float t = fmaf(k, dt, t0);
+        const KParams &P = F->P;
+        const float x = fmaf(t, dx, P.eye[0]);
+        const float y = fmaf(t, dy, P.eye[1]);
+        const float w = fmaf(t, dz, P.eye[2]);
+        if (AXIS && closed_first) {
+          const float s0 = fmaf(w, w, y * y);
+          const float tx = x + x;
+          const float a0 = fmaf(x, x, c[0] - s0);
+          z.a1 = fmaf(tx, y, c[1]);
+          z.a2 = fmaf(tx, w, c[2]);
+          z.a3 = c[3];
+          z.b0 = c[4];
+          z.b1 = c[5];
+          z.b2 = c[6];
+          z.b3 = c[7];
+          s = fmaf(z.a2, z.a2, fmaf(z.a1, z.a1, c3sq));
+          const bool esc1 = fmaf(a0, a0, s + cdsq) > R2;
+          z.a0 = esc1 ? 1e18f : a0;
+          n = esc1 ? 0 : 1;
+        } else {
+          start_point<AXIS>(P, x, y, w, z, s);
+          n = 0;
+        }
+      }
+      if (!fast) {
+        {
+          const KParams &P = F->P;
+          const bool inside = !esc;
+          const int m = n;
+          it_lane += (uint32_t)m;
+          bool next_normal = false;
+          bool restart = false;   // start the point at parameter tr on the ray
+          float tr = 0.0f;
+          if (phase == PH_MARCH) {
+            if (inside) {
+              kstar = (int)k;
+              if (kstar == 0) {
+                thit = t0;
+                next_normal = true;
+              } else {
+                lo = fmaf(k - 1.0f, dt, t0);
+                hi = fmaf(k, dt, t0);
+                if (P.B == 0) {
+                  thit = 0.5f * (lo + hi);
+                  next_normal = true;
+                } else {
+                  b = 0;
+                  phase = PH_BISECT;
+                  tr = 0.5f * (lo + hi);
+                  restart = true;
+                }
+              }
+            } else {  // last sample was outside: the ray misses
+              write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+              phase = PH_IDLE;
+            }
+          } else if (phase == PH_BISECT) {
+            const float tm = 0.5f * (lo + hi);
+            if (inside)
+              hi = tm;
+            else
+              lo = tm;
+            ++b;
+            if (b >= P.B) {
+              thit = 0.5f * (lo + hi);
+              next_normal = true;
+            } else {
+              tr = 0.5f * (lo + hi);
+              restart = true;
+            }
+          } else {  // PH_NORMAL: stencil point sidx just retired
+            const float G = potential(n2, m);
+            const float sg = (sidx & 1) ? -G : G;
+            const int axis = sidx >> 1;
+            if (axis == 0)
+              gx += sg;
+            else if (axis == 1)
+              gy += sg;
+            else
+              gz += sg;
+            ++sidx;
+            if (sidx == 6) {
+              const float g[3] = {gx, gy, gz};
+              const float d[3] = {dx, dy, dz};
+              PixelOut r;
+              finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+              write_pixel(F->out, pix, r);
+              phase = PH_IDLE;
+            }
+          }
+          if (next_normal) {
+            phase = PH_NORMAL;
+            sidx = 0;
+            gx = gy = gz = 0.0f;
+          }
+          float px = 0, py = 0, pz = 0;
+          if (restart) {
+            px = fmaf(tr, dx, P.eye[0]);
+            py = fmaf(tr, dy, P.eye[1]);
+            pz = fmaf(tr, dz, P.eye[2]);
+          } else if (phase == PH_NORMAL) {
+            const int axis = sidx >> 1;
+            const float hs = (sidx & 1) ? -P.h : P.h;
+            px = fmaf(thit, dx, P.eye[0]) + (axis == 0 ? hs : 0.0f);
+            py = fmaf(thit, dy, P.eye[1]) + (axis == 1 ? hs : 0.0f);
+            pz = fmaf(thit, dz, P.eye[2]) + (axis == 2 ? hs : 0.0f);
+          }
+          if (phase != PH_IDLE) {
+            start_point<AXIS>(P, px, py, pz, z, s);
+            n = 0;
+          }
+        }
+      }
+    }
+
+    // ---- hand new rays to idle lanes
+    for (;;) {
+      const uint64_t idle = __builtin_amdgcn_ballot_w64(phase == PH_IDLE);
+      if (!idle) break;
+      if (!have_tile) {
+        if (exhausted) break;
+        if (!pending) {
+          uint32_t t = 0;
+          if (lane == 0) t = atomicAdd(counter, 1u);
+          t = uniform(t);
+          if (t >= total_tiles) {
+            exhausted = true;
+            break;
+          }
+          pend_tile = t;
+          pending = true;
+        }
+        const int f = BATCH ? find_frame(table, nframes, pend_tile) : 0;
+        if (f != frame) {
+          if (idle != ~0ull) break;  // finish this frame's rays first
+          if (frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+          it_lane = 0;
+          frame = f;
+          if (BATCH) F = table + f;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) c[q] = F->P.c[q];
+          R2 = F->P.R2;
+          N = F->P.N;
+          Sf = (float)F->P.S;
+          c3sq = c[3] * c[3];
+          closed_first = AXIS && N > 1;
+          cdsq = NORM == 0 ? fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))) : 0.0f;
+        }
+        tile_local = pend_tile - F->tile_begin;
+        pending = false;
+        have_tile = true;
+        next_r = 0;
+      }
+      const int rank = rank_in(idle);
+      const int avail = tile_rays - next_r;
+      if (phase == PH_IDLE && rank < avail) {
+        const KParams &P = F->P;
+        const int r = next_r + rank;
+        const int i = (int)(tile_local % F->tiles_x) * TW + r % TW;
+        const int j = (int)(tile_local / F->tiles_x) * TH + r / TW;
+        if (i < P.W && j < P.H) {
+          pix = j * P.W + i;
+          float d[3];
+          pixel_dir(P, i, j, d);
+          float ta, tb;
+          if (clip_box(P, d, ta, tb)) {
+            dx = d[0];
+            dy = d[1];
+            dz = d[2];
+            t0 = ta;
+            dt = (tb - ta) / (float)P.S;
+            // Enter the march as if sample -1 had just escaped: the fast path then
+            // starts sample 0. Its fictitious update is not counted.
+            k = -1.0f;
+            kstar = -1;
+            phase = PH_MARCH;
+            // (an idle lane's state may have overflowed to inf/NaN: reset all of it)
+            z = DQ<float>{1e18f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            s = 0.0f;
+            n = 0;
+            it_lane -= 1u;
+          } else {
+            write_pixel(F->out, pix, miss_pixel(0));
+          }
+        }
+      }
+      const int cnt = __popcll(idle);
+      next_r += cnt < avail ? cnt : avail;
+      if (next_r >= tile_rays) have_tile = false;
+    }
+
+    if (exhausted && !__builtin_amdgcn_ballot_w64(phase != PH_IDLE)) break;
+  }
+  if (frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+}
+
+__global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
+
+template <bool BATCH>
+static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *table, int nframes,
+                                     uint32_t total_tiles, int norm, bool axis, uint32_t *counter,
+                                     const Sched &s, int cus, hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+  const int threads = 64 * s.waves_per_block;
+  const int blocks = cus * s.blocks_per_cu;
+#define DQJ_LAUNCH(NM, AX)                                                                   \
+  hipLaunchKernelGGL((render_refill_kernel<NM, AX, BATCH>), dim3(blocks), dim3(threads), 0,   \
+                     stream, single, table, nframes, total_tiles, counter, s.tile_w, s.tile_h)
+  if (norm == 0) {
+    if (axis)
+      DQJ_LAUNCH(0, true);
+    else
+      DQJ_LAUNCH(0, false);
+  } else {
+    if (axis)
+      DQJ_LAUNCH(1, true);
+    else
+      DQJ_LAUNCH(1, false);
+  }
+#undef DQJ_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
+                                hipStream_t stream) {
+  return launch_refill_impl<false>(frame, nullptr, 1, frame.ntiles, frame.P.norm,
+                                   frame.P.axis_slice != 0, counter, s, cus, stream);
+}
+
+hipError_t launch_render_refill_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
+                                      int norm, bool all_axis, uint32_t *counter, const Sched &s,
+                                      int cus, hipStream_t stream) {
+  FrameDesc dummy;
+  memset(&dummy, 0, sizeof dummy);
+  return launch_refill_impl<true>(dummy, table_dev, nframes, total_tiles, norm, all_axis, counter, s,
+                                  cus, stream);
+}
+
+}  // namespace dqj

@@ -1,0 +1,34 @@
+// runtime_internal.h -- host helpers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dqj.h"
+#include "kparams.h"
+
+namespace dqj {
+
+dqj_status fail(dqj_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+dqj_status hip_fail(hipError_t e, const char *what);
+dqj_status current_device(int *dev, int *cus);
+dqj_status validate_params(const dqj_params *p);
+dqj_status validate_out(const dqj_frame_out *o);
+void pack_params(const dqj_params &p, KParams &k);
+KOut to_kout(const dqj_frame_out &o);
+
+// Schedule actually used by a launch (defaults and limits applied).
+struct Sched {
+  int kernel;           // DQJ_KERNEL_REFILL or DQJ_KERNEL_DIRECT
+  int tile_w, tile_h;
+  int waves_per_block;
+  int blocks_per_cu;
+};
+Sched resolve_schedule(const dqj_schedule *s, int cus);
+
+// FP32 render of one frame with a schedule (s may be null: defaults).
+hipError_t launch_render_fp32(const KParams &P, const KOut &out, const Sched &s, int cus,
+                              hipStream_t stream);
+
+// Device word private to (current device, stream) for persistent-kernel tile counters.
+hipError_t stream_counter(hipStream_t stream, uint32_t **out);
+
+}  // namespace dqj

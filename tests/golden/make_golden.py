@@ -1,0 +1,41 @@
+"""Write the stored expected values under tests/golden/ from the FP64 oracle only.
+
+ialg_plain_1024.json: for the 1024x1024 workload (3 seeded c, max_iter 24, 512 march
+steps, 10 bisection steps), the number of dual-quaternion updates the method runs
+per frame (march samples through the first inside one, bisection, 6 normal samples,
+each to escape or max_iter), plus hit counts. The benchmark divides this count by
+the GPU time to report Julia iterations per second.
+
+Run:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle      # noqa: E402
+import workloads   # noqa: E402
+
+
+def main():
+    frames = []
+    t = time.time()
+    for seed, p in zip((0, 1, 2), workloads.plain_1024()):
+        r = oracle.render(p)
+        frames.append({"seed": seed, "c": p.c, "iters": r["total_iters"],
+                       "hits": int(r["mask"].sum())})
+        print(frames[-1], flush=True)
+    out = {"workload": "plain_1024", "width": 1024, "height": 1024, "max_iter": 24,
+           "march_steps": 512, "bisect_steps": 10, "frames": frames,
+           "total_iters": sum(f["iters"] for f in frames),
+           "generator": "tests/golden/make_golden.py (FP64 oracle)",
+           "oracle_seconds": round(time.time() - t, 1)}
+    with open(os.path.join(HERE, "ialg_plain_1024.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,104 @@
+"""Test-side comparison of GPU frames with the FP64 oracle.
+
+A pixel AGREES if both miss, or both hit with |depth_gpu - depth_oracle| <= 1e-4 E,
+E the box diagonal. Every other pixel is a mismatch; at most 0.1 % may mismatch,
+and each must lie within one march step of the set's boundary: the FP64 fine scan
+(64 points) of [t - dt, t + dt] around the disputed sample t must change class.
+The disputed sample is the earlier first-inside sample of the two sides (the one
+whose class the two sides disagree on). On agreeing hits the shade must be within
+1/255 (the fraction within is returned as well).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+import oracle
+import workloads
+
+
+def to_numpy(out: Dict) -> Dict[str, np.ndarray]:
+    r = {}
+    for k, v in out.items():
+        if hasattr(v, "detach"):
+            v = v.detach().cpu().numpy()
+        r[k] = v
+    return r
+
+
+def compare(p, gpu: Dict[str, np.ndarray], ora: Dict[str, np.ndarray],
+            pixels: Optional[np.ndarray] = None, scan: bool = True, max_scan: int = 400):
+    """Compare GPU outputs (full images) with oracle outputs (full images, or flat
+    arrays for the listed ``pixels``). Returns a report dict."""
+    E = workloads.scene_extent(p)
+    tol = 1e-4 * E
+    if pixels is None:
+        g = {k: np.asarray(v).reshape(-1, *np.asarray(v).shape[2:]) for k, v in gpu.items()
+             if k in ("mask", "depth", "shade", "first_hit", "normal")}
+        o = {k: np.asarray(ora[k]).reshape(g[k].shape) for k in g}
+        idx = np.arange(p.width * p.height)
+    else:
+        idx = np.asarray(pixels)
+        g = {k: np.asarray(gpu[k]).reshape(-1, *np.asarray(gpu[k]).shape[2:])[idx] for k in
+             ("mask", "depth", "shade", "first_hit") if k in gpu}
+        o = {k: np.asarray(ora[k]) for k in g}
+    gm = g["mask"].astype(bool)
+    om = o["mask"].astype(bool)
+    both_hit = gm & om
+    ddepth = np.where(both_hit, np.abs(g["depth"].astype(np.float64) - o["depth"]), 0.0)
+    agree = (~gm & ~om) | (both_hit & (ddepth <= tol))
+    mism = np.nonzero(~agree)[0]
+    rep = {
+        "pixels": int(idx.size),
+        "hits_gpu": int(gm.sum()),
+        "hits_oracle": int(om.sum()),
+        "agree_frac": float(agree.mean()),
+        "mismatches": int(mism.size),
+        "depth_err_max_E": float(ddepth[both_hit & agree].max() / E) if (both_hit & agree).any() else 0.0,
+    }
+    sh_ok = both_hit & agree
+    if sh_ok.any():
+        ds = np.abs(g["shade"].astype(np.float64) - o["shade"])[sh_ok]
+        rep["shade_err_max"] = float(ds.max())
+        rep["shade_within_frac"] = float((ds <= 1.0 / 255.0).mean())
+        rep["shade_err_p999"] = float(np.quantile(ds, 0.999))
+    else:
+        rep["shade_err_max"] = 0.0
+        rep["shade_within_frac"] = 1.0
+        rep["shade_err_p999"] = 0.0
+    # mismatch diagnosis: the disputed sample must sit within one march step of a class change
+    far = []
+    if scan and "first_hit" in g:
+        for q in mism[:max_scan]:
+            pix = int(idx[q])
+            i, j = pix % p.width, pix // p.width
+            hit, o3, d3, t0, t1 = oracle.ray(p, i, j)
+            if not hit:
+                far.append(pix)
+                continue
+            dt = (t1 - t0) / p.march_steps
+            ks = [int(k) for k in (g["first_hit"][q], o["first_hit"][q]) if k >= 0]
+            if not ks:
+                far.append(pix)
+                continue
+            kd = min(ks)
+            td = t0 + kd * dt
+            _, changes = oracle.scan_ray(p, i, j, td - dt, td + dt, 64)
+            if changes == 0:
+                far.append(pix)
+    rep["mismatch_far_from_boundary"] = far
+    return rep
+
+
+def assert_parity(rep, min_agree=0.999, shade_frac=0.999):
+    assert rep["agree_frac"] >= min_agree, rep
+    assert not rep["mismatch_far_from_boundary"], rep
+    assert rep["depth_err_max_E"] <= 1e-4, rep
+    assert rep["shade_within_frac"] >= shade_frac, rep
+
+
+def sample_pixels(p, n: int, seed: int = 0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(p.width * p.height, size=min(n, p.width * p.height), replace=False))
