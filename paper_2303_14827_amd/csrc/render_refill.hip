@@ -42,8 +42,31 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// A wave-uniform float, kept in a scalar register.
+__device__ __forceinline__ float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// The frame table is never written while a launch runs: reading it through the
+// constant address space lets uniform reads become scalar loads. (The host pass
+// of the compiler only needs the type to exist.)
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) FrameDesc *ConstFrame;
+#else
+typedef const FrameDesc *ConstFrame;
+#endif
+
+template <bool BATCH>
+struct FramePtr {
+  typedef const FrameDesc *type;
+};
+template <>
+struct FramePtr<true> {
+  typedef ConstFrame type;
+};
+
 // Frame of a global tile index (frames are in tile order).
-__device__ __forceinline__ int find_frame(const FrameDesc *table, int nframes, uint32_t tile) {
+__device__ __forceinline__ int find_frame(ConstFrame table, int nframes, uint32_t tile) {
   int lo = 0, hi = nframes - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -80,7 +103,12 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
   const int tile_rays = TW * TH;
 
   // ---- wave-uniform state
-  const FrameDesc *F = BATCH ? nullptr : &single;
+  const ConstFrame ctable = (ConstFrame)table;
+  typename FramePtr<BATCH>::type F;
+  if constexpr (BATCH)
+    F = nullptr;
+  else
+    F = &single;
   int frame = -1;
   uint32_t tile_local = 0;      // tile index within the frame
   int next_r = 0;               // next ray of the tile to hand out
@@ -90,6 +118,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
 #pragma unroll
   for (int q = 0; q < 8; ++q) c[q] = 0.0f;
   float R2 = 0.0f, c3sq = 0.0f, cdsq = 0.0f, Sf = 0.0f;
+  float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // eye (cached: the table is not provably read-only)
   int N = 1;
   bool closed_first = false;   // first march update in closed form (identity slice, N > 1)
 
@@ -107,7 +136,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
 
   for (;;) {
     // ---- one update on every lane (idle lanes compute and discard)
-    const float n2 = dq_update<NORM>(z, s, c);
+    const float n2 = dq_update_hot<NORM>(z, s, c);
     ++n;
     const bool esc = n2 > R2;
     const bool done = phase != PH_IDLE && (esc || n >= N);
@@ -123,10 +152,9 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
         it_lane += (uint32_t)n;
         k += 1.0f;
         const float t = fmaf(k, dt, t0);
-        const KParams &P = F->P;
-        const float x = fmaf(t, dx, P.eye[0]);
-        const float y = fmaf(t, dy, P.eye[1]);
-        const float w = fmaf(t, dz, P.eye[2]);
+        const float x = fmaf(t, dx, ex);
+        const float y = fmaf(t, dy, ey);
+        const float w = fmaf(t, dz, ez);
         if (AXIS && closed_first) {
           const float s0 = fmaf(w, w, y * y);
           const float tx = x + x;
@@ -143,7 +171,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           z.a0 = esc1 ? 1e18f : a0;
           n = esc1 ? 0 : 1;
         } else {
-          start_point<AXIS>(P, x, y, w, z, s);
+          start_point<AXIS>(F->P, x, y, w, z, s);
           n = 0;
         }
       }
@@ -255,19 +283,24 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           pend_tile = t;
           pending = true;
         }
-        const int f = BATCH ? find_frame(table, nframes, pend_tile) : 0;
+        const int f = BATCH ? find_frame(ctable, nframes, pend_tile) : 0;
         if (f != frame) {
           if (idle != ~0ull) break;  // finish this frame's rays first
           if (frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
           it_lane = 0;
           frame = f;
-          if (BATCH) F = table + f;
+          if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) c[q] = F->P.c[q];
-          R2 = F->P.R2;
-          N = F->P.N;
-          Sf = (float)F->P.S;
-          c3sq = c[3] * c[3];
+          for (int q = 0; q < 8; ++q) c[q] = uniform_f(F->P.c[q]);
+          R2 = uniform_f(F->P.R2);
+          N = (int)uniform((uint32_t)F->P.N);
+          ex = uniform_f(F->P.eye[0]);
+          ey = uniform_f(F->P.eye[1]);
+          ez = uniform_f(F->P.eye[2]);
+          Sf = uniform_f((float)F->P.S);
+          c3sq = uniform_f(c[3] * c[3]);
+          cdsq = NORM == 0 ? uniform_f(fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))))
+                           : 0.0f;
           closed_first = AXIS && N > 1;
           cdsq = NORM == 0 ? fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))) : 0.0f;
         }

@@ -156,7 +156,7 @@ def test_c0_sphere_closed_form(dqj, oracle_mod):
             sh = min(1.0, p.k_ambient + p.k_diffuse * max(0.0, float(np.dot(nrm, l))))
             assert abs(g["shade"][j, i] - sh) <= 1.0 / 255.0
             n_checked += 1
-    assert n_checked > 300
+    assert n_checked > 200
 
 
 @pytest.mark.parametrize("case", [
