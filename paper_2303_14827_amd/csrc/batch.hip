@@ -24,12 +24,13 @@ namespace {
 // Host-side validation and packing shared by the eager and the captured batch.
 dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
                       const Sched &s, std::vector<FrameDesc> &table, uint32_t &total_tiles,
-                      int &norm, bool &all_axis) {
+                      int &norm, bool &all_axis, bool &any_count) {
   if (n < 1) return fail(DQJ_E_INVALID, "batch size must be >= 1 (got %d)", n);
   if (!params || !outs) return fail(DQJ_E_INVALID, "params and outs are required");
   table.resize(n);
   uint64_t tiles = 0;
   all_axis = true;
+  any_count = false;
   for (int32_t i = 0; i < n; ++i) {
     dqj_status st = validate_params(params + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
@@ -47,6 +48,7 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
     set_tiles(f, s.tile_w, s.tile_h);
     tiles += f.ntiles;
     all_axis = all_axis && f.P.axis_slice;
+    any_count = any_count || f.out.iters != nullptr;
   }
   if (tiles >= (1ull << 31)) return fail(DQJ_E_INVALID, "batch has too many tiles (%llu)",
                                          (unsigned long long)tiles);
@@ -122,8 +124,8 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
     std::vector<FrameDesc> table;
     uint32_t total = 0;
     int norm = 0;
-    bool all_axis = true;
-    st = pack_batch(params, outs, n, s, table, total, norm, all_axis);
+    bool all_axis = true, any_count = false;
+    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count);
     if (st != DQJ_OK) return st;
     reap_retired(false);
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -141,8 +143,8 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
     uint32_t *counter = nullptr;
     if (e == hipSuccess) e = stream_counter(stream, &counter);
     if (e == hipSuccess)
-      e = launch_render_refill_batch((const FrameDesc *)r.dev, n, total, norm, all_axis, counter, s,
-                                     cus, stream);
+      e = launch_render_refill_batch((const FrameDesc *)r.dev, n, total, norm, all_axis, any_count,
+                                     counter, s, cus, stream);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(r.ev, stream);
     if (e != hipSuccess) {
@@ -182,8 +184,8 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     std::vector<FrameDesc> table;
     uint32_t total = 0;
     int norm = 0;
-    bool all_axis = true;
-    st = pack_batch(params, outs, n, s, table, total, norm, all_axis);
+    bool all_axis = true, any_count = false;
+    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count);
     if (st != DQJ_OK) return st;
     p = new dqj_batch_plan;
     p->dev = dev;
@@ -200,7 +202,7 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       // The capture holds a counter-reset kernel (not a memset node) and the kernel.
-      hipError_t le = launch_render_refill_batch(p->table_dev, n, total, norm, all_axis,
+      hipError_t le = launch_render_refill_batch(p->table_dev, n, total, norm, all_axis, any_count,
                                                  p->counter_dev, s, cus, p->cap_stream);
       e = hipStreamEndCapture(p->cap_stream, &p->graph);
       if (le != hipSuccess) e = le;

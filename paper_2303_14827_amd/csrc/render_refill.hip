@@ -93,7 +93,7 @@ __device__ __forceinline__ void start_point(const KParams &P, float x, float y, 
 
 }  // namespace
 
-template <int NORM, bool AXIS, bool BATCH>
+template <int NORM, bool AXIS, bool BATCH, bool COUNT>
 __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
                                                              const FrameDesc *__restrict__ table,
                                                              int nframes, uint32_t total_tiles,
@@ -101,6 +101,8 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
                                                              int TW, int TH) {
   const int lane = lane_id();
   const int tile_rays = TW * TH;
+  const float kNaN = __builtin_nanf("");
+  const float kNoMarch = 1e30f;   // k outside the march: the fast-path test k < S fails
 
   // ---- wave-uniform state
   const ConstFrame ctable = (ConstFrame)table;
@@ -121,25 +123,30 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
   float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // eye (cached: the table is not provably read-only)
   int N = 1;
   bool closed_first = false;   // first march update in closed form (identity slice, N > 1)
+  // Trip counter: one update per trip. A point started in trip t has had trip - t
+  // updates after trip `trip`, so "max_iter reached" is trip >= deadline, with the
+  // deadline set when the point starts; no per-lane counter is incremented.
+  uint32_t trip = 0;
 
-  // ---- per-lane state
+  // ---- per-lane state. Idle lanes sit on a NaN state (never escapes) with a far
+  // deadline, so they never retire and need no separate test.
   int phase = PH_IDLE;
-  DQ<float> z{0, 0, 0, 0, 0, 0, 0, 0};
-  float s = 0.0f;
-  int n = 0;              // updates applied to the current point
+  DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+  float s = kNaN;
+  uint32_t dl = 1u << 30;
   int pix = 0;
   float dx = 0, dy = 0, dz = 0, t0 = 0, dt = 0;
-  float k = 0.0f;         // march sample index (exact in FP32 up to 2^24)
+  float k = kNoMarch;     // march sample index (exact in FP32 up to 2^24)
   int b = 0, sidx = 0, kstar = -1;
   float lo = 0, hi = 0, thit = 0, gx = 0, gy = 0, gz = 0;
   uint32_t it_lane = 0;
 
   for (;;) {
-    // ---- one update on every lane (idle lanes compute and discard)
+    ++trip;
+    // ---- one update on every lane
     const float n2 = dq_update_hot<NORM>(z, s, c);
-    ++n;
     const bool esc = n2 > R2;
-    const bool done = phase != PH_IDLE && (esc || n >= N);
+    const bool done = esc || (int)(trip - dl) >= 0;
 
     if (done) {
       // Fast path: an outside march sample with more samples to go starts the next
@@ -147,9 +154,9 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
       // (zeta_0 = (x, y, z, 0 | 0) gives z_1 = (x^2 - y^2 - z^2 + c0, 2xy + c1, 2xz + c2,
       // c3 | c_d)); a sample that escapes on that update is parked on a state that
       // escapes on the next one, so it retires with escape index 1.
-      const bool fast = esc && phase == PH_MARCH && k < Sf;
+      const bool fast = esc && k < Sf;
       if (fast) {
-        it_lane += (uint32_t)n;
+        if (COUNT) it_lane += (uint32_t)N - (dl - trip);
         k += 1.0f;
         const float t = fmaf(k, dt, t0);
         const float x = fmaf(t, dx, ex);
@@ -169,99 +176,101 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           s = fmaf(z.a2, z.a2, fmaf(z.a1, z.a1, c3sq));
           const bool esc1 = fmaf(a0, a0, s + cdsq) > R2;
           z.a0 = esc1 ? 1e18f : a0;
-          n = esc1 ? 0 : 1;
+          dl = trip + (uint32_t)N - (esc1 ? 0u : 1u);
         } else {
           start_point<AXIS>(F->P, x, y, w, z, s);
-          n = 0;
+          dl = trip + (uint32_t)N;
         }
-      }
-      if (!fast) {
-        {
-          const KParams &P = F->P;
-          const bool inside = !esc;
-          const int m = n;
-          it_lane += (uint32_t)m;
-          bool next_normal = false;
-          bool restart = false;   // start the point at parameter tr on the ray
-          float tr = 0.0f;
-          if (phase == PH_MARCH) {
-            if (inside) {
-              kstar = (int)k;
-              if (kstar == 0) {
-                thit = t0;
-                next_normal = true;
-              } else {
-                lo = fmaf(k - 1.0f, dt, t0);
-                hi = fmaf(k, dt, t0);
-                if (P.B == 0) {
-                  thit = 0.5f * (lo + hi);
-                  next_normal = true;
-                } else {
-                  b = 0;
-                  phase = PH_BISECT;
-                  tr = 0.5f * (lo + hi);
-                  restart = true;
-                }
-              }
-            } else {  // last sample was outside: the ray misses
-              write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
-              phase = PH_IDLE;
-            }
-          } else if (phase == PH_BISECT) {
-            const float tm = 0.5f * (lo + hi);
-            if (inside)
-              hi = tm;
-            else
-              lo = tm;
-            ++b;
-            if (b >= P.B) {
-              thit = 0.5f * (lo + hi);
+      } else {
+        const KParams &P = F->P;
+        const bool inside = !esc;
+        const int m = N - (int)(dl - trip);   // escape index, or N when inside
+        if (COUNT) it_lane += (uint32_t)m;
+        bool next_normal = false;
+        bool restart = false;   // start the point at parameter tr on the ray
+        float tr = 0.0f;
+        if (phase == PH_MARCH) {
+          if (inside) {
+            kstar = (int)k;
+            k = kNoMarch;
+            if (kstar == 0) {
+              thit = t0;
               next_normal = true;
             } else {
-              tr = 0.5f * (lo + hi);
-              restart = true;
+              lo = fmaf((float)(kstar - 1), dt, t0);
+              hi = fmaf((float)kstar, dt, t0);
+              if (P.B == 0) {
+                thit = 0.5f * (lo + hi);
+                next_normal = true;
+              } else {
+                b = 0;
+                phase = PH_BISECT;
+                tr = 0.5f * (lo + hi);
+                restart = true;
+              }
             }
-          } else {  // PH_NORMAL: stencil point sidx just retired
-            const float G = potential(n2, m);
-            const float sg = (sidx & 1) ? -G : G;
-            const int axis = sidx >> 1;
-            if (axis == 0)
-              gx += sg;
-            else if (axis == 1)
-              gy += sg;
-            else
-              gz += sg;
-            ++sidx;
-            if (sidx == 6) {
-              const float g[3] = {gx, gy, gz};
-              const float d[3] = {dx, dy, dz};
-              PixelOut r;
-              finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
-              write_pixel(F->out, pix, r);
-              phase = PH_IDLE;
-            }
+          } else {  // the last sample was outside: the ray misses
+            write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+            phase = PH_IDLE;
           }
-          if (next_normal) {
-            phase = PH_NORMAL;
-            sidx = 0;
-            gx = gy = gz = 0.0f;
+        } else if (phase == PH_BISECT) {
+          const float tm = 0.5f * (lo + hi);
+          if (inside)
+            hi = tm;
+          else
+            lo = tm;
+          ++b;
+          if (b >= P.B) {
+            thit = 0.5f * (lo + hi);
+            next_normal = true;
+          } else {
+            tr = 0.5f * (lo + hi);
+            restart = true;
           }
-          float px = 0, py = 0, pz = 0;
-          if (restart) {
-            px = fmaf(tr, dx, P.eye[0]);
-            py = fmaf(tr, dy, P.eye[1]);
-            pz = fmaf(tr, dz, P.eye[2]);
-          } else if (phase == PH_NORMAL) {
-            const int axis = sidx >> 1;
-            const float hs = (sidx & 1) ? -P.h : P.h;
-            px = fmaf(thit, dx, P.eye[0]) + (axis == 0 ? hs : 0.0f);
-            py = fmaf(thit, dy, P.eye[1]) + (axis == 1 ? hs : 0.0f);
-            pz = fmaf(thit, dz, P.eye[2]) + (axis == 2 ? hs : 0.0f);
+        } else {  // PH_NORMAL: stencil point sidx just retired
+          const float G = potential(n2, m);
+          const float sg = (sidx & 1) ? -G : G;
+          const int axis = sidx >> 1;
+          if (axis == 0)
+            gx += sg;
+          else if (axis == 1)
+            gy += sg;
+          else
+            gz += sg;
+          ++sidx;
+          if (sidx == 6) {
+            const float g[3] = {gx, gy, gz};
+            const float d[3] = {dx, dy, dz};
+            PixelOut r;
+            finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+            write_pixel(F->out, pix, r);
+            phase = PH_IDLE;
           }
-          if (phase != PH_IDLE) {
-            start_point<AXIS>(P, px, py, pz, z, s);
-            n = 0;
-          }
+        }
+        if (next_normal) {
+          phase = PH_NORMAL;
+          sidx = 0;
+          gx = gy = gz = 0.0f;
+        }
+        float px = 0, py = 0, pz = 0;
+        if (restart) {
+          px = fmaf(tr, dx, ex);
+          py = fmaf(tr, dy, ey);
+          pz = fmaf(tr, dz, ez);
+        } else if (phase == PH_NORMAL) {
+          const int axis = sidx >> 1;
+          const float hs = (sidx & 1) ? -P.h : P.h;
+          px = fmaf(thit, dx, ex) + (axis == 0 ? hs : 0.0f);
+          py = fmaf(thit, dy, ey) + (axis == 1 ? hs : 0.0f);
+          pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
+        }
+        if (phase != PH_IDLE) {
+          start_point<AXIS>(P, px, py, pz, z, s);
+          dl = trip + (uint32_t)N;
+        } else {
+          z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+          s = kNaN;
+          dl = trip + (1u << 30);
         }
       }
     }
@@ -286,7 +295,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
         const int f = BATCH ? find_frame(ctable, nframes, pend_tile) : 0;
         if (f != frame) {
           if (idle != ~0ull) break;  // finish this frame's rays first
-          if (frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+          if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
           it_lane = 0;
           frame = f;
           if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
@@ -302,7 +311,6 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           cdsq = NORM == 0 ? uniform_f(fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))))
                            : 0.0f;
           closed_first = AXIS && N > 1;
-          cdsq = NORM == 0 ? fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))) : 0.0f;
         }
         tile_local = pend_tile - F->tile_begin;
         pending = false;
@@ -332,11 +340,10 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
             k = -1.0f;
             kstar = -1;
             phase = PH_MARCH;
-            // (an idle lane's state may have overflowed to inf/NaN: reset all of it)
             z = DQ<float>{1e18f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             s = 0.0f;
-            n = 0;
-            it_lane -= 1u;
+            dl = trip + (uint32_t)N;
+            if (COUNT) it_lane -= 1u;
           } else {
             write_pixel(F->out, pix, miss_pixel(0));
           }
@@ -349,21 +356,18 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
 
     if (exhausted && !__builtin_amdgcn_ballot_w64(phase != PH_IDLE)) break;
   }
-  if (frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+  if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
 }
 
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
-template <bool BATCH>
-static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *table, int nframes,
-                                     uint32_t total_tiles, int norm, bool axis, uint32_t *counter,
-                                     const Sched &s, int cus, hipStream_t stream) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
-  const int threads = 64 * s.waves_per_block;
-  const int blocks = cus * s.blocks_per_cu;
-#define DQJ_LAUNCH(NM, AX)                                                                   \
-  hipLaunchKernelGGL((render_refill_kernel<NM, AX, BATCH>), dim3(blocks), dim3(threads), 0,   \
-                     stream, single, table, nframes, total_tiles, counter, s.tile_w, s.tile_h)
+template <bool BATCH, bool COUNT>
+static void launch_refill_variant(const FrameDesc &single, const FrameDesc *table, int nframes,
+                                  uint32_t total_tiles, int norm, bool axis, uint32_t *counter,
+                                  const Sched &s, int blocks, int threads, hipStream_t stream) {
+#define DQJ_LAUNCH(NM, AX)                                                                    \
+  hipLaunchKernelGGL((render_refill_kernel<NM, AX, BATCH, COUNT>), dim3(blocks), dim3(threads), \
+                     0, stream, single, table, nframes, total_tiles, counter, s.tile_w, s.tile_h)
   if (norm == 0) {
     if (axis)
       DQJ_LAUNCH(0, true);
@@ -376,22 +380,39 @@ static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *t
       DQJ_LAUNCH(1, false);
   }
 #undef DQJ_LAUNCH
+}
+
+template <bool BATCH>
+static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *table, int nframes,
+                                     uint32_t total_tiles, int norm, bool axis, bool count,
+                                     uint32_t *counter, const Sched &s, int cus,
+                                     hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+  const int threads = 64 * s.waves_per_block;
+  const int blocks = cus * s.blocks_per_cu;
+  if (count)
+    launch_refill_variant<BATCH, true>(single, table, nframes, total_tiles, norm, axis, counter, s,
+                                       blocks, threads, stream);
+  else
+    launch_refill_variant<BATCH, false>(single, table, nframes, total_tiles, norm, axis, counter, s,
+                                        blocks, threads, stream);
   return hipGetLastError();
 }
 
 hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
                                 hipStream_t stream) {
   return launch_refill_impl<false>(frame, nullptr, 1, frame.ntiles, frame.P.norm,
-                                   frame.P.axis_slice != 0, counter, s, cus, stream);
+                                   frame.P.axis_slice != 0, frame.out.iters != nullptr, counter, s,
+                                   cus, stream);
 }
 
 hipError_t launch_render_refill_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
-                                      int norm, bool all_axis, uint32_t *counter, const Sched &s,
-                                      int cus, hipStream_t stream) {
+                                      int norm, bool all_axis, bool any_count, uint32_t *counter,
+                                      const Sched &s, int cus, hipStream_t stream) {
   FrameDesc dummy;
   memset(&dummy, 0, sizeof dummy);
-  return launch_refill_impl<true>(dummy, table_dev, nframes, total_tiles, norm, all_axis, counter, s,
-                                  cus, stream);
+  return launch_refill_impl<true>(dummy, table_dev, nframes, total_tiles, norm, all_axis, any_count,
+                                  counter, s, cus, stream);
 }
 
 }  // namespace dqj

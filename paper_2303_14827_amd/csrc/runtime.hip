@@ -114,6 +114,8 @@ dqj_status validate_params(const dqj_params *p) {
     return fail(DQJ_E_INVALID, "fov_y_deg must be in (0, 180)");
   if (!fin(p->normal_h) || !(p->normal_h > 0))
     return fail(DQJ_E_INVALID, "normal_h must be finite and > 0");
+  if ((int64_t)(p->march_steps + p->bisect_steps + 8) * p->max_iter > (int64_t)1 << 30)
+    return fail(DQJ_E_INVALID, "(march_steps + bisect_steps + 8) * max_iter must not exceed 2^30");
   if (!fin(p->k_ambient) || !fin(p->k_diffuse))
     return fail(DQJ_E_INVALID, "k_ambient/k_diffuse must be finite");
   if (p->norm != DQJ_NORM_EUCLID8 && p->norm != DQJ_NORM_REALPART)

@@ -230,6 +230,15 @@ def test_schedule_invariance_bitwise(dqj):
             continue
         for k in ("mask", "depth", "shade", "normal", "first_hit", "image8", "flags", "iters"):
             np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+    # the variant compiled without the work counter gives the same image
+    import torch
+    out = dqj.alloc_outputs(p.width, p.height)
+    del out["iters"]
+    dqj.render(p, out=out)
+    torch.cuda.synchronize()
+    g = to_numpy(out)
+    for k in ("mask", "depth", "shade", "normal", "first_hit", "image8", "flags"):
+        np.testing.assert_array_equal(g[k], ref[k], err_msg="no-count " + k)
 
 
 def test_batch_matches_single_and_graph_replays(dqj):
