@@ -15,6 +15,7 @@
 #include "dqj.h"
 #include "kparams.h"
 #include "refill.h"
+#include "split.h"
 #include "runtime_internal.h"
 
 namespace dqj {
@@ -24,26 +25,32 @@ namespace {
 // Host-side validation and packing shared by the eager and the captured batch.
 dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
                       const Sched &s, std::vector<FrameDesc> &table, uint32_t &total_tiles,
-                      int &norm, bool &all_axis, bool &any_count) {
+                      int &norm, bool &all_axis, bool &any_count, int &precision,
+                      uint64_t &pixels) {
   if (n < 1) return fail(DQJ_E_INVALID, "batch size must be >= 1 (got %d)", n);
   if (!params || !outs) return fail(DQJ_E_INVALID, "params and outs are required");
   table.resize(n);
   uint64_t tiles = 0;
   all_axis = true;
   any_count = false;
+  pixels = 0;
   for (int32_t i = 0; i < n; ++i) {
     dqj_status st = validate_params(params + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
     st = validate_out(outs + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
-    if (params[i].precision != DQJ_PREC_FP32)
-      return fail(DQJ_E_UNSUPPORTED, "frame %d: batched renders run in FP32", i);
+    if (params[i].precision != DQJ_PREC_FP32 && params[i].precision != DQJ_PREC_SPLIT)
+      return fail(DQJ_E_UNSUPPORTED, "frame %d: batched renders run in FP32 or split precision", i);
+    if (i > 0 && params[i].precision != params[0].precision)
+      return fail(DQJ_E_INVALID, "frame %d: all frames of a batch must share precision", i);
     if (i > 0 && params[i].norm != params[0].norm)
       return fail(DQJ_E_INVALID, "frame %d: all frames of a batch must share the escape norm", i);
     FrameDesc &f = table[i];
     memset(&f, 0, sizeof f);
     pack_params(params[i], f.P);
+    pack_params64(params[i], f.P64);
     f.out = to_kout(outs[i]);
+    pixels += (uint64_t)params[i].width * (uint64_t)params[i].height;
     f.tile_begin = (uint32_t)tiles;
     set_tiles(f, s.tile_w, s.tile_h);
     tiles += f.ntiles;
@@ -54,6 +61,7 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
                                          (unsigned long long)tiles);
   total_tiles = (uint32_t)tiles;
   norm = params[0].norm;
+  precision = params[0].precision;
   return DQJ_OK;
 }
 
@@ -93,6 +101,7 @@ struct dqj_batch_plan {
   int dev = 0;
   FrameDesc *table_dev = nullptr;
   uint32_t *counter_dev = nullptr;
+  void *split_scratch = nullptr;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -109,6 +118,7 @@ static void plan_free(dqj_batch_plan *p) {
   if (p->done) (void)hipEventDestroy(p->done);
   if (p->table_dev) (void)hipFree(p->table_dev);
   if (p->counter_dev) (void)hipFree(p->counter_dev);
+  if (p->split_scratch) (void)hipFree(p->split_scratch);
   delete p;
 }
 
@@ -125,7 +135,9 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
     uint32_t total = 0;
     int norm = 0;
     bool all_axis = true, any_count = false;
-    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count);
+    int precision = 0;
+    uint64_t pixels = 0;
+    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count, precision, pixels);
     if (st != DQJ_OK) return st;
     reap_retired(false);
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -140,11 +152,19 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
       return fail(DQJ_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
     e = hipMemcpyAsync(r.dev, r.host, bytes, hipMemcpyHostToDevice, stream);
-    uint32_t *counter = nullptr;
-    if (e == hipSuccess) e = stream_counter(stream, &counter);
-    if (e == hipSuccess)
-      e = launch_render_refill_batch((const FrameDesc *)r.dev, n, total, norm, all_axis, any_count,
-                                     counter, s, cus, stream);
+    if (precision == DQJ_PREC_FP32) {
+      uint32_t *counter = nullptr;
+      if (e == hipSuccess) e = stream_counter(stream, &counter);
+      if (e == hipSuccess)
+        e = launch_render_refill_batch((const FrameDesc *)r.dev, n, total, norm, all_axis,
+                                       any_count, counter, s, cus, stream);
+    } else {
+      void *scratch = nullptr;
+      if (e == hipSuccess) e = stream_scratch(stream, split_scratch_bytes(pixels), &scratch);
+      if (e == hipSuccess)
+        e = launch_render_split_batch((const FrameDesc *)r.dev, n, total, norm, all_axis, any_count,
+                                      split_scratch_at(scratch, pixels), s, cus, stream);
+    }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(r.ev, stream);
     if (e != hipSuccess) {
@@ -185,7 +205,9 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     uint32_t total = 0;
     int norm = 0;
     bool all_axis = true, any_count = false;
-    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count);
+    int precision = 0;
+    uint64_t pixels = 0;
+    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count, precision, pixels);
     if (st != DQJ_OK) return st;
     p = new dqj_batch_plan;
     p->dev = dev;
@@ -196,14 +218,21 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
       return fail(DQJ_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
     e = hipMalloc(&p->counter_dev, 256);
+    if (e == hipSuccess && precision == DQJ_PREC_SPLIT)
+      e = hipMalloc(&p->split_scratch, split_scratch_bytes(pixels));
     if (e == hipSuccess) e = hipMemcpy(p->table_dev, table.data(), bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       // The capture holds a counter-reset kernel (not a memset node) and the kernel.
-      hipError_t le = launch_render_refill_batch(p->table_dev, n, total, norm, all_axis, any_count,
-                                                 p->counter_dev, s, cus, p->cap_stream);
+      hipError_t le =
+          precision == DQJ_PREC_FP32
+              ? launch_render_refill_batch(p->table_dev, n, total, norm, all_axis, any_count,
+                                           p->counter_dev, s, cus, p->cap_stream)
+              : launch_render_split_batch(p->table_dev, n, total, norm, all_axis, any_count,
+                                          split_scratch_at(p->split_scratch, pixels), s, cus,
+                                          p->cap_stream);
       e = hipStreamEndCapture(p->cap_stream, &p->graph);
       if (le != hipSuccess) e = le;
     }

@@ -37,6 +37,18 @@ struct alignas(16) KParams {
 };
 static_assert(sizeof(KParams) % 16 == 0, "KParams must be 16-byte sized");
 
+// The same frame in FP64 (camera basis and derived constants never rounded to FP32),
+// for the FP64 re-bisection of the split-precision path and FP64 classification.
+struct alignas(16) KParams64 {
+  double c[8];
+  double so[8], su[8], sv[8], sw[8];
+  double eye[3], fwd[3], right[3], up[3];
+  double bmin[3], bmax[3];
+  double light[3];
+  double sx_scale, sy_scale, inv_w, inv_h;
+  double R2, h, ka, kd;
+};
+
 // What one frame writes (device pointers; optional ones may be null).
 struct KOut {
   uint8_t *mask;
@@ -53,6 +65,7 @@ struct KOut {
 // outputs, and where its tiles sit in the launch's global tile sequence.
 struct alignas(16) FrameDesc {
   KParams P;
+  KParams64 P64;
   KOut out;
   uint32_t tile_begin;   // first global tile index of this frame
   uint32_t tiles_x;      // tiles per image row

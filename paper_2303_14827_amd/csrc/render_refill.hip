@@ -181,7 +181,11 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           start_point<AXIS>(F->P, x, y, w, z, s);
           dl = trip + (uint32_t)N;
         }
-      } else {
+      }
+      // Everything else (a march hit or miss, a bisection or normal point) is rare: a
+      // separate wave-uniform test keeps its code off the fast path (an if/else here
+      // makes the compiler copy the lane state at the join on every trip).
+      if (done && !fast) {
         const KParams &P = F->P;
         const bool inside = !esc;
         const int m = N - (int)(dl - trip);   // escape index, or N when inside

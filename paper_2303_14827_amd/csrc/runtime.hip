@@ -14,6 +14,7 @@
 #include "kparams.h"
 #include "launch.h"
 #include "refill.h"
+#include "split.h"
 #include "runtime_internal.h"
 
 namespace dqj {
@@ -207,6 +208,46 @@ void pack_params(const dqj_params &p, KParams &k) {
   k.fp64_window = p.fp64_window;
 }
 
+void pack_params64(const dqj_params &p, KParams64 &k) {
+  memset(&k, 0, sizeof k);
+  for (int i = 0; i < 8; ++i) {
+    k.c[i] = p.c[i];
+    k.so[i] = p.slice_origin[i];
+    k.su[i] = p.slice_axes[0][i];
+    k.sv[i] = p.slice_axes[1][i];
+    k.sw[i] = p.slice_axes[2][i];
+  }
+  double f[3] = {p.target[0] - p.eye[0], p.target[1] - p.eye[1], p.target[2] - p.eye[2]};
+  const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  for (double &x : f) x /= fl;
+  double r[3] = {f[1] * p.up[2] - f[2] * p.up[1], f[2] * p.up[0] - f[0] * p.up[2],
+                 f[0] * p.up[1] - f[1] * p.up[0]};
+  const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  for (double &x : r) x /= rl;
+  const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2],
+                       r[0] * f[1] - r[1] * f[0]};
+  const double tan_half = std::tan(0.5 * p.fov_y_deg * M_PI / 180.0);
+  const double ll = std::sqrt(p.light_dir[0] * p.light_dir[0] + p.light_dir[1] * p.light_dir[1] +
+                              p.light_dir[2] * p.light_dir[2]);
+  for (int i = 0; i < 3; ++i) {
+    k.eye[i] = p.eye[i];
+    k.fwd[i] = f[i];
+    k.right[i] = r[i];
+    k.up[i] = u[i];
+    k.bmin[i] = p.box_min[i];
+    k.bmax[i] = p.box_max[i];
+    k.light[i] = p.light_dir[i] / ll;
+  }
+  k.sx_scale = tan_half * (double)p.width / (double)p.height;
+  k.sy_scale = tan_half;
+  k.inv_w = 1.0 / p.width;
+  k.inv_h = 1.0 / p.height;
+  k.R2 = p.escape_radius * p.escape_radius;
+  k.h = p.normal_h;
+  k.ka = p.k_ambient;
+  k.kd = p.k_diffuse;
+}
+
 KOut to_kout(const dqj_frame_out &o) {
   KOut k;
   k.mask = o.mask;
@@ -262,25 +303,56 @@ struct StreamSlot {
   int dev;
   hipStream_t stream;
   uint32_t *counter;
+  void *scratch;
+  size_t scratch_bytes;
 };
 static std::mutex g_slot_mu;
 static std::vector<StreamSlot> g_slots;
+
+static StreamSlot *find_slot(int dev, hipStream_t stream, hipError_t *err) {
+  for (StreamSlot &s : g_slots)
+    if (s.dev == dev && s.stream == stream) return &s;
+  void *p = nullptr;
+  *err = hipMalloc(&p, 256);
+  if (*err != hipSuccess) return nullptr;
+  g_slots.push_back(StreamSlot{dev, stream, (uint32_t *)p, nullptr, 0});
+  return &g_slots.back();
+}
 
 hipError_t stream_counter(hipStream_t stream, uint32_t **out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lk(g_slot_mu);
-  for (const StreamSlot &s : g_slots)
-    if (s.dev == dev && s.stream == stream) {
-      *out = s.counter;
-      return hipSuccess;
-    }
-  void *p = nullptr;
-  e = hipMalloc(&p, 256);
+  StreamSlot *s = find_slot(dev, stream, &e);
+  if (!s) return e;
+  *out = s->counter;
+  return hipSuccess;
+}
+
+// Device scratch private to (current device, stream), grown on demand. Work on one
+// stream is ordered, so reuse by the next call on the stream is safe; growing first
+// waits for the stream so the old block is no longer in use.
+hipError_t stream_scratch(hipStream_t stream, size_t bytes, void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  g_slots.push_back(StreamSlot{dev, stream, (uint32_t *)p});
-  *out = (uint32_t *)p;
+  std::lock_guard<std::mutex> lk(g_slot_mu);
+  StreamSlot *s = find_slot(dev, stream, &e);
+  if (!s) return e;
+  if (s->scratch_bytes < bytes) {
+    if (s->scratch) {
+      e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) return e;
+      (void)hipFree(s->scratch);
+      s->scratch = nullptr;
+      s->scratch_bytes = 0;
+    }
+    e = hipMalloc(&s->scratch, bytes);
+    if (e != hipSuccess) return e;
+    s->scratch_bytes = bytes;
+  }
+  *out = s->scratch;
   return hipSuccess;
 }
 
@@ -289,7 +361,7 @@ hipError_t launch_render_fp32(const KParams &P, const KOut &out, const Sched &s,
   if (s.kernel == DQJ_KERNEL_DIRECT) return launch_render_direct(P, out, stream);
   FrameDesc f;
   memset(&f, 0, sizeof f);
-  f.P = P;
+  f.P = P;  // P64 is unused by the FP32 kernels
   f.out = out;
   f.tile_begin = 0;
   set_tiles(f, s.tile_w, s.tile_h);
@@ -318,6 +390,22 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
     case DQJ_PREC_FP32:
       e = launch_render_fp32(kp, ko, resolve_schedule(sched, cus), cus, stream);
       break;
+    case DQJ_PREC_SPLIT: {
+      const Sched s = resolve_schedule(sched, cus);
+      FrameDesc f;
+      memset(&f, 0, sizeof f);
+      f.P = kp;
+      pack_params64(*params, f.P64);
+      f.out = ko;
+      f.tile_begin = 0;
+      set_tiles(f, s.tile_w, s.tile_h);
+      const uint64_t pixels = (uint64_t)params->width * (uint64_t)params->height;
+      void *scratch = nullptr;
+      e = stream_scratch(stream, split_scratch_bytes(pixels), &scratch);
+      if (e != hipSuccess) return fail(DQJ_E_NOMEM, "split scratch: %s", hipGetErrorString(e));
+      e = launch_render_split(f, split_scratch_at(scratch, pixels), s, cus, stream);
+      break;
+    }
     default:
       return fail(DQJ_E_UNSUPPORTED, "precision %d is not offered by dqj_render",
                   params->precision);

@@ -13,6 +13,7 @@ dqj_status current_device(int *dev, int *cus);
 dqj_status validate_params(const dqj_params *p);
 dqj_status validate_out(const dqj_frame_out *o);
 void pack_params(const dqj_params &p, KParams &k);
+void pack_params64(const dqj_params &p, KParams64 &k);
 KOut to_kout(const dqj_frame_out &o);
 
 // Schedule actually used by a launch (defaults and limits applied).
@@ -30,5 +31,8 @@ hipError_t launch_render_fp32(const KParams &P, const KOut &out, const Sched &s,
 
 // Device word private to (current device, stream) for persistent-kernel tile counters.
 hipError_t stream_counter(hipStream_t stream, uint32_t **out);
+
+// Device scratch of at least `bytes` private to (current device, stream).
+hipError_t stream_scratch(hipStream_t stream, size_t bytes, void **out);
 
 }  // namespace dqj

@@ -1,0 +1,46 @@
+// split.h -- split-precision launchers and their device scratch (library-internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kparams.h"
+#include "runtime_internal.h"
+
+namespace dqj {
+
+// A ray the FP16 march found inside at sample khat (hit list), or one whose FP32
+// window check was ambiguous (FP64 list).
+struct SplitEntry {
+  uint32_t frame;
+  uint32_t pix;
+  int32_t khat;
+  uint32_t pad;
+};
+
+// Device scratch of one split launch: ctr[0] tile counter, ctr[1] hit-list length,
+// ctr[2] ambiguous-list length; each list holds up to one entry per pixel.
+struct SplitScratch {
+  uint32_t *ctr;
+  SplitEntry *hits;
+  SplitEntry *amb;
+};
+
+inline size_t split_scratch_bytes(uint64_t pixels) {
+  return 256 + 2 * sizeof(SplitEntry) * (size_t)pixels;
+}
+
+inline SplitScratch split_scratch_at(void *base, uint64_t pixels) {
+  SplitScratch s;
+  s.ctr = (uint32_t *)base;
+  s.hits = (SplitEntry *)((char *)base + 256);
+  s.amb = s.hits + pixels;
+  return s;
+}
+
+hipError_t launch_render_split(const FrameDesc &frame, const SplitScratch &sc, const Sched &s,
+                               int cus, hipStream_t stream);
+hipError_t launch_render_split_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
+                                     int norm, bool all_axis, bool any_count,
+                                     const SplitScratch &sc, const Sched &s, int cus,
+                                     hipStream_t stream);
+
+}  // namespace dqj

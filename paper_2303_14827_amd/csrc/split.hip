@@ -1,0 +1,610 @@
+// split.hip -- split-precision form of the ray march.
+//
+//   1. march_fp16: the fixed-step march (section "Ray-Marching") in packed FP16. A lane
+//      owns a ray and classifies two consecutive samples k, k+1 per packed register
+//      (half2), so every v_pk_fma_f16 advances two samples. Escape is tracked as the
+//      running maximum of ||z_n||^2 (v_pk_max_f16 ignores NaN, so an escaped half stays
+//      escaped after it overflows), which is exactly "||z_n||^2 > R^2 for some n <= N".
+//      The first inside FP16 sample k^ of each ray goes to a compacted hit list; rays
+//      with no inside sample are written as misses.
+//   2. refine_fp32: for each listed ray, classify the window k^-w .. k^+w in FP32. If the
+//      FP32 classes there are monotone (out ... out in ... in) and agree with FP16 at
+//      k^-1 and k^, bisect [t_{k^-1}, t_{k^}] in FP32, take the central-difference normal
+//      and shade. Otherwise the ray is ambiguous and goes to a second list.
+//   3. rebisect_fp64: for each ambiguous ray, classify the window in FP64, take its first
+//      inside sample (marching on past the window in FP64 if there is none), then bisect,
+//      take the normal and shade in FP64.
+// The three kernels run back to back on one stream; list lengths stay on the device.
+#include <cstring>
+
+#include "dq_device.h"
+#include "launch.h"
+#include "refill.h"
+#include "split.h"
+
+namespace dqj {
+
+namespace {
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+struct DQH {
+  h2 a0, a1, a2, a3, b0, b1, b2, b3;
+};
+
+__device__ __forceinline__ h2 hfma(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }
+__device__ __forceinline__ h2 hsplat(float v) { return h2{(_Float16)v, (_Float16)v}; }
+
+// One packed update of two independent points (one per half), as dq_update.
+template <int NORM>
+__device__ __forceinline__ h2 pk_update(DQH &z, h2 &s, const h2 *c) {
+  const h2 ta = z.a0 + z.a0;
+  const h2 tb = z.b0 + z.b0;
+  const h2 dot = hfma(z.a3, z.b3, hfma(z.a2, z.b2, z.a1 * z.b1));
+  z.b1 = hfma(tb, z.a1, hfma(ta, z.b1, c[5]));
+  z.b2 = hfma(tb, z.a2, hfma(ta, z.b2, c[6]));
+  z.b3 = hfma(tb, z.a3, hfma(ta, z.b3, c[7]));
+  z.b0 = hfma(hsplat(-2.0f), dot, hfma(ta, z.b0, c[4]));
+  z.a1 = hfma(ta, z.a1, c[1]);
+  z.a2 = hfma(ta, z.a2, c[2]);
+  z.a3 = hfma(ta, z.a3, c[3]);
+  z.a0 = hfma(z.a0, z.a0, c[0]) - s;
+  s = hfma(z.a3, z.a3, hfma(z.a2, z.a2, z.a1 * z.a1));
+  h2 n2 = hfma(z.a0, z.a0, s);
+  if (NORM == 0) n2 = hfma(z.b3, z.b3, hfma(z.b2, z.b2, hfma(z.b1, z.b1, hfma(z.b0, z.b0, n2))));
+  return n2;
+}
+
+__device__ __forceinline__ int rank_in(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) FrameDesc *ConstFrame;
+#else
+typedef const FrameDesc *ConstFrame;
+#endif
+
+template <bool BATCH>
+struct FramePtr {
+  typedef const FrameDesc *type;
+};
+template <>
+struct FramePtr<true> {
+  typedef ConstFrame type;
+};
+
+__device__ __forceinline__ int find_frame(ConstFrame table, int nframes, uint32_t tile) {
+  int lo = 0, hi = nframes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].tile_begin <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Pixel direction in FP64 (for the FP64 pass).
+__device__ __forceinline__ void pixel_dir64(const KParams64 &P, int i, int j, double d[3]) {
+  const double sx = ((double)(2 * i + 1) * P.inv_w - 1.0) * P.sx_scale;
+  const double sy = (1.0 - (double)(2 * j + 1) * P.inv_h) * P.sy_scale;
+  double v[3];
+  for (int k = 0; k < 3; ++k) v[k] = P.fwd[k] + sx * P.right[k] + sy * P.up[k];
+  const double inv = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  d[0] = v[0] * inv;
+  d[1] = v[1] * inv;
+  d[2] = v[2] * inv;
+}
+
+__device__ __forceinline__ bool clip_box64(const KParams64 &P, const double d[3], double &t0,
+                                           double &t1) {
+  double tn = 0.0, tf = INFINITY;
+  for (int k = 0; k < 3; ++k) {
+    const double o = P.eye[k];
+    if (d[k] == 0.0) {
+      if (o < P.bmin[k] || o > P.bmax[k]) return false;
+      continue;
+    }
+    double ta = (P.bmin[k] - o) / d[k];
+    double tb = (P.bmax[k] - o) / d[k];
+    if (ta > tb) {
+      const double s = ta;
+      ta = tb;
+      tb = s;
+    }
+    tn = ta > tn ? ta : tn;
+    tf = tb < tf ? tb : tf;
+  }
+  if (tn > tf) return false;
+  t0 = tn;
+  t1 = tf;
+  return true;
+}
+
+template <typename P_T, typename T>
+__device__ __forceinline__ DQ<T> slice_map_t(const P_T &P, T x, T y, T z) {
+  T v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = T(P.so[k]) + x * T(P.su[k]) + y * T(P.sv[k]) + z * T(P.sw[k]);
+  return DQ<T>{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+}
+
+// Classify the world point eye + t d (precision T). Returns the escape index m
+// (N when inside) and sets *inside and *n2.
+template <int NORM, typename P_T, typename T>
+__device__ __forceinline__ int classify_t(const P_T &P, const T *c, int N, T R2, T t, const T d[3],
+                                          T hx, T hy, T hz, bool *inside, T *n2) {
+  DQ<T> z = slice_map_t<P_T, T>(P, fma(t, d[0], T(P.eye[0])) + hx, fma(t, d[1], T(P.eye[1])) + hy,
+                                fma(t, d[2], T(P.eye[2])) + hz);
+  const int m = dq_classify<NORM>(z, c, N, R2, n2);
+  *inside = m == 0;
+  return m ? m : N;
+}
+
+// Bisection + central-difference normal + shade for a hit at sample k (precision T).
+template <int NORM, typename P_T, typename T>
+__device__ __forceinline__ uint32_t finish_ray(const P_T &P, const T *c, int N, int B, T R2, T h,
+                                               const T d[3], T t0, T dt, int k, uint8_t flags,
+                                               PixelOut &r) {
+  uint32_t it = 0;
+  T thit;
+  if (k == 0) {
+    thit = t0;
+  } else {
+    T lo = fma(T(k - 1), dt, t0), hi = fma(T(k), dt, t0);
+    for (int b = 0; b < B; ++b) {
+      const T tm = T(0.5) * (lo + hi);
+      bool in;
+      T n2;
+      it += classify_t<NORM>(P, c, N, R2, tm, d, T(0), T(0), T(0), &in, &n2);
+      if (in)
+        hi = tm;
+      else
+        lo = tm;
+    }
+    thit = T(0.5) * (lo + hi);
+  }
+  T g[3];
+  for (int a = 0; a < 3; ++a) {
+    T gp = T(0);
+    for (int sg = 0; sg < 2; ++sg) {
+      const T hs = sg == 0 ? h : -h;
+      bool in;
+      T n2;
+      const int m = classify_t<NORM>(P, c, N, R2, thit, d, a == 0 ? hs : T(0), a == 1 ? hs : T(0),
+                                     a == 2 ? hs : T(0), &in, &n2);
+      it += m;
+      const T G = potential(n2, m);
+      gp = sg == 0 ? G : gp - G;
+    }
+    g[a] = gp;
+  }
+  // shade with this precision's light and coefficients
+  const T gl = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  T n[3];
+  if (gl > T(0) && isfinite(gl)) {
+    n[0] = g[0] / gl;
+    n[1] = g[1] / gl;
+    n[2] = g[2] / gl;
+  } else {
+    n[0] = -d[0];
+    n[1] = -d[1];
+    n[2] = -d[2];
+    flags |= DQJ_FLAG_FALLBACK;
+  }
+  T ndl = n[0] * T(P.light[0]) + n[1] * T(P.light[1]) + n[2] * T(P.light[2]);
+  ndl = ndl > T(0) ? ndl : T(0);
+  T sh = T(P.ka) + T(P.kd) * ndl;
+  sh = sh < T(0) ? T(0) : (sh > T(1) ? T(1) : sh);
+  r.depth = (float)thit;
+  r.shade = (float)sh;
+  r.nx = (float)n[0];
+  r.ny = (float)n[1];
+  r.nz = (float)n[2];
+  r.first_hit = k;
+  r.mask = 1;
+  r.flags = flags;
+  return it;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// 1. FP16 march
+// ---------------------------------------------------------------------------
+template <int NORM, bool AXIS, bool BATCH, bool COUNT>
+__global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
+                                                          const FrameDesc *__restrict__ table,
+                                                          int nframes, uint32_t total_tiles,
+                                                          uint32_t *__restrict__ ctr,
+                                                          SplitEntry *__restrict__ hits, int TW,
+                                                          int TH) {
+  const int lane = lane_id();
+  const int tile_rays = TW * TH;
+  const ConstFrame ctable = (ConstFrame)table;
+  typename FramePtr<BATCH>::type F;
+  if constexpr (BATCH)
+    F = nullptr;
+  else
+    F = &single;
+  int frame = -1;
+  uint32_t tile_local = 0;
+  int next_r = 0;
+  bool have_tile = false, pending = false, exhausted = false;
+  uint32_t pend_tile = 0;
+  h2 c[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) c[q] = hsplat(0.0f);
+  h2 c3sq = hsplat(0.0f), cdsq = hsplat(0.0f);
+  _Float16 R2 = 0;
+  float Sf = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  int N = 1;
+  bool closed_first = false;
+  uint32_t trip = 0;
+
+  bool busy = false;
+  DQH z;
+  z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = hsplat(0.0f);
+  h2 s = hsplat(0.0f), m2 = hsplat(0.0f);
+  uint32_t dl = 1u << 30;
+  int pix = 0;
+  float dx = 0, dy = 0, dz = 0, t0 = 0, dt = 0, kp = 0.0f;   // kp: low sample of the pair
+  uint32_t cnt_lo = 0, cnt_hi = 0, it_lane = 0;
+
+  for (;;) {
+    ++trip;
+    if (COUNT) {
+      cnt_lo += (m2.x <= R2) ? 1u : 0u;
+      cnt_hi += (m2.y <= R2) ? 1u : 0u;
+    }
+    const h2 n2 = pk_update<NORM>(z, s, c);
+    m2 = __builtin_elementwise_max(m2, n2);
+    const bool esc_lo = m2.x > R2, esc_hi = m2.y > R2;
+    const bool done = busy && ((esc_lo && esc_hi) || (int)(trip - dl) >= 0);
+    if (done) {
+      bool start = false;
+      if (esc_lo && esc_hi && kp + 2.0f <= Sf) {   // both outside: next pair
+        if (COUNT) it_lane += cnt_lo + cnt_hi;
+        kp += 2.0f;
+        start = true;
+      } else {
+        if (esc_lo && esc_hi) {
+          if (COUNT) it_lane += cnt_lo + cnt_hi;
+          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+        } else {
+          if (COUNT) it_lane += cnt_lo + (esc_lo ? cnt_hi : 0u);
+          const uint32_t slot = atomicAdd(ctr + 1, 1u);
+          hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, (int32_t)kp + (esc_lo ? 1 : 0), 0u};
+        }
+        busy = false;
+        m2 = hsplat(0.0f);
+        dl = trip + (1u << 30);
+      }
+      if (start) {
+        const float tl = fmaf(kp, dt, t0), th = fmaf(kp + 1.0f, dt, t0);
+        const h2 xh = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fmaf(tl, dx, ex), fmaf(th, dx, ex)));
+        const h2 yh = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fmaf(tl, dy, ey), fmaf(th, dy, ey)));
+        const h2 wh = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fmaf(tl, dz, ez), fmaf(th, dz, ez)));
+        if (AXIS && closed_first) {
+          // z_1 of (x, y, w, 0 | 0) in closed form; m2 starts at ||z_1||^2
+          const h2 s0 = hfma(wh, wh, yh * yh);
+          const h2 tx = xh + xh;
+          z.a0 = hfma(xh, xh, c[0] - s0);
+          z.a1 = hfma(tx, yh, c[1]);
+          z.a2 = hfma(tx, wh, c[2]);
+          z.a3 = c[3];
+          z.b0 = c[4];
+          z.b1 = c[5];
+          z.b2 = c[6];
+          z.b3 = c[7];
+          s = hfma(z.a2, z.a2, hfma(z.a1, z.a1, c3sq));
+          m2 = hfma(z.a0, z.a0, s + cdsq);
+          dl = trip + (uint32_t)N - 1u;
+          if (COUNT) cnt_lo = cnt_hi = 1;
+        } else {
+          const KParams &P = F->P;
+          const float xl = fmaf(tl, dx, ex), xhh = fmaf(th, dx, ex);
+          const float yl = fmaf(tl, dy, ey), yhh = fmaf(th, dy, ey);
+          const float wl = fmaf(tl, dz, ez), whh = fmaf(th, dz, ez);
+          const DQ<float> zl = slice_map<float>(P, xl, yl, wl);
+          const DQ<float> zh = slice_map<float>(P, xhh, yhh, whh);
+#define DQJ_PK(F_) __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(zl.F_, zh.F_))
+          z.a0 = DQJ_PK(a0);
+          z.a1 = DQJ_PK(a1);
+          z.a2 = DQJ_PK(a2);
+          z.a3 = DQJ_PK(a3);
+          z.b0 = DQJ_PK(b0);
+          z.b1 = DQJ_PK(b1);
+          z.b2 = DQJ_PK(b2);
+          z.b3 = DQJ_PK(b3);
+#undef DQJ_PK
+          s = hfma(z.a3, z.a3, hfma(z.a2, z.a2, z.a1 * z.a1));
+          m2 = hsplat(0.0f);
+          dl = trip + (uint32_t)N;
+          if (COUNT) cnt_lo = cnt_hi = 0;
+        }
+        if (kp + 1.0f > Sf) {   // the pair's high half is past the last sample
+          m2.y = (_Float16)INFINITY;
+          if (COUNT) cnt_hi = 0;
+        }
+      }
+    }
+
+    // ---- hand new rays to idle lanes
+    for (;;) {
+      const uint64_t idle = __builtin_amdgcn_ballot_w64(!busy);
+      if (!idle) break;
+      if (!have_tile) {
+        if (exhausted) break;
+        if (!pending) {
+          uint32_t t = 0;
+          if (lane == 0) t = atomicAdd(ctr, 1u);
+          t = uniform(t);
+          if (t >= total_tiles) {
+            exhausted = true;
+            break;
+          }
+          pend_tile = t;
+          pending = true;
+        }
+        const int f = BATCH ? find_frame(ctable, nframes, pend_tile) : 0;
+        if (f != frame) {
+          if (idle != ~0ull) break;
+          if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+          it_lane = 0;
+          frame = f;
+          if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
+          float cf[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            cf[q] = uniform_f(F->P.c[q]);
+            c[q] = hsplat(cf[q]);
+          }
+          R2 = (_Float16)uniform_f(F->P.R2);
+          N = (int)uniform((uint32_t)F->P.N);
+          ex = uniform_f(F->P.eye[0]);
+          ey = uniform_f(F->P.eye[1]);
+          ez = uniform_f(F->P.eye[2]);
+          Sf = uniform_f((float)F->P.S);
+          c3sq = hsplat(cf[3] * cf[3]);
+          cdsq = hsplat(NORM == 0 ? cf[4] * cf[4] + cf[5] * cf[5] + cf[6] * cf[6] + cf[7] * cf[7] : 0.0f);
+          closed_first = AXIS && N > 1;
+        }
+        tile_local = pend_tile - F->tile_begin;
+        pending = false;
+        have_tile = true;
+        next_r = 0;
+      }
+      const int rank = rank_in(idle);
+      const int avail = tile_rays - next_r;
+      if (!busy && rank < avail) {
+        const KParams &P = F->P;
+        const int r = next_r + rank;
+        const int i = (int)(tile_local % F->tiles_x) * TW + r % TW;
+        const int j = (int)(tile_local / F->tiles_x) * TH + r / TW;
+        if (i < P.W && j < P.H) {
+          pix = j * P.W + i;
+          float d[3];
+          pixel_dir(P, i, j, d);
+          float ta, tb;
+          if (clip_box(P, d, ta, tb)) {
+            dx = d[0];
+            dy = d[1];
+            dz = d[2];
+            t0 = ta;
+            dt = (tb - ta) / (float)P.S;
+            // enter as if the pair (-2, -1) had just escaped: the next trip starts pair 0
+            kp = -2.0f;
+            busy = true;
+            m2 = hsplat(65504.0f);
+            z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = hsplat(0.0f);
+            s = hsplat(0.0f);
+            dl = trip + (uint32_t)N;
+            if (COUNT) cnt_lo = cnt_hi = 0;
+          } else {
+            write_pixel(F->out, pix, miss_pixel(0));
+          }
+        }
+      }
+      const int cntw = __popcll(idle);
+      next_r += cntw < avail ? cntw : avail;
+      if (next_r >= tile_rays) have_tile = false;
+    }
+    if (exhausted && !__builtin_amdgcn_ballot_w64(busy)) break;
+  }
+  if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+}
+
+// ---------------------------------------------------------------------------
+// 2. FP32 verify window + bisection + normal + shade over the hit list
+// ---------------------------------------------------------------------------
+template <int NORM, bool BATCH, bool COUNT>
+__global__ __launch_bounds__(256) void refine_fp32_kernel(FrameDesc single,
+                                                          const FrameDesc *__restrict__ table,
+                                                          const uint32_t *__restrict__ ctr,
+                                                          const SplitEntry *__restrict__ hits,
+                                                          uint32_t *__restrict__ amb_ctr,
+                                                          SplitEntry *__restrict__ amb) {
+  const ConstFrame ctable = (ConstFrame)table;
+  const uint32_t n = ctr[1];
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const SplitEntry en = hits[e];
+    const FrameDesc *Fg = nullptr;
+    typename FramePtr<BATCH>::type F;
+    if constexpr (BATCH)
+      F = ctable + en.frame;
+    else
+      F = &single;
+    (void)Fg;
+    const KParams &P = F->P;
+    const int i = (int)(en.pix % (uint32_t)P.W), j = (int)(en.pix / (uint32_t)P.W);
+    float d[3], t0, t1;
+    pixel_dir(P, i, j, d);
+    clip_box(P, d, t0, t1);
+    const float dt = (t1 - t0) / (float)P.S;
+    const int w = P.fp64_window;
+    const int kh = en.khat;
+    const int klo = kh - w > 0 ? kh - w : 0;
+    const int khi = kh + w < P.S ? kh + w : P.S;
+    uint32_t in_mask = 0, it = 0;
+    for (int k = klo; k <= khi; ++k) {
+      bool in;
+      float n2;
+      it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)k, dt, t0), d, 0.0f, 0.0f, 0.0f, &in, &n2);
+      in_mask |= (in ? 1u : 0u) << (k - klo);
+    }
+    // monotone: every bit above the lowest set bit is set (up to khi)
+    const uint32_t full = (2u << (khi - klo)) - 1u;
+    const uint32_t low = in_mask & (0u - in_mask);
+    const bool monotone = in_mask != 0 && ((in_mask | (low - 1u)) == full);
+    const bool agree = ((in_mask >> (kh - klo)) & 1u) &&
+                       (kh == 0 || !((in_mask >> (kh - 1 - klo)) & 1u));
+    if (monotone && agree) {
+      PixelOut r;
+      it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, kh,
+                             (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+      write_pixel(F->out, en.pix, r);
+    } else {
+      const uint32_t slot = atomicAdd(amb_ctr, 1u);
+      amb[slot] = en;
+    }
+    if (COUNT && F->out.iters) atomicAdd(F->out.iters, (unsigned long long)it);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. FP64 re-march of the window and re-bisection over the ambiguous list
+// ---------------------------------------------------------------------------
+template <int NORM, bool BATCH, bool COUNT>
+__global__ __launch_bounds__(256) void rebisect_fp64_kernel(FrameDesc single,
+                                                            const FrameDesc *__restrict__ table,
+                                                            const uint32_t *__restrict__ amb_ctr,
+                                                            const SplitEntry *__restrict__ amb) {
+  const ConstFrame ctable = (ConstFrame)table;
+  const uint32_t n = *amb_ctr;
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const SplitEntry en = amb[e];
+    typename FramePtr<BATCH>::type F;
+    if constexpr (BATCH)
+      F = ctable + en.frame;
+    else
+      F = &single;
+    const KParams64 &Q = F->P64;
+    const int W = F->P.W, S = F->P.S, N = F->P.N, B = F->P.B;
+    const int i = (int)(en.pix % (uint32_t)W), j = (int)(en.pix / (uint32_t)W);
+    double d[3], t0, t1;
+    pixel_dir64(Q, i, j, d);
+    uint32_t it = 0;
+    PixelOut r;
+    if (!clip_box64(Q, d, t0, t1)) {
+      r = miss_pixel(DQJ_FLAG_FP64);
+    } else {
+      const double dt = (t1 - t0) / (double)S;
+      const int w = F->P.fp64_window;
+      const int klo = en.khat - w > 0 ? en.khat - w : 0;
+      int kstar = -1;
+      for (int k = klo; k <= S; ++k) {
+        bool in;
+        double n2;
+        it += classify_t<NORM>(Q, Q.c, N, Q.R2, fma((double)k, dt, t0), d, 0.0, 0.0, 0.0, &in, &n2);
+        if (in) {
+          kstar = k;
+          break;
+        }
+      }
+      if (kstar < 0) {
+        r = miss_pixel(DQJ_FLAG_BOX | DQJ_FLAG_FP64);
+      } else {
+        it += finish_ray<NORM>(Q, Q.c, N, B, Q.R2, Q.h, d, t0, dt, kstar,
+                               (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT | DQJ_FLAG_FP64), r);
+      }
+    }
+    write_pixel(F->out, en.pix, r);
+    if (COUNT && F->out.iters) atomicAdd(F->out.iters, (unsigned long long)it);
+  }
+}
+
+__global__ void reset_split_counters_kernel(uint32_t *ctr) {
+  if (threadIdx.x < 4) ctr[threadIdx.x] = 0u;
+}
+
+template <bool BATCH, bool COUNT>
+static void launch_split_variant(const FrameDesc &single, const FrameDesc *table, int nframes,
+                                 uint32_t total_tiles, int norm, bool axis, const SplitScratch &sc,
+                                 const Sched &s, int cus, hipStream_t stream) {
+  const int threads = 64 * s.waves_per_block;
+  const int blocks = cus * s.blocks_per_cu;
+#define DQJ_MARCH(NM, AX)                                                                     \
+  hipLaunchKernelGGL((march_fp16_kernel<NM, AX, BATCH, COUNT>), dim3(blocks), dim3(threads), 0, \
+                     stream, single, table, nframes, total_tiles, sc.ctr, sc.hits, s.tile_w,     \
+                     s.tile_h)
+  if (norm == 0) {
+    if (axis)
+      DQJ_MARCH(0, true);
+    else
+      DQJ_MARCH(0, false);
+  } else {
+    if (axis)
+      DQJ_MARCH(1, true);
+    else
+      DQJ_MARCH(1, false);
+  }
+#undef DQJ_MARCH
+  const int rblocks = cus * 8;
+  if (norm == 0) {
+    hipLaunchKernelGGL((refine_fp32_kernel<0, BATCH, COUNT>), dim3(rblocks), dim3(256), 0, stream,
+                       single, table, sc.ctr, sc.hits, sc.ctr + 2, sc.amb);
+    hipLaunchKernelGGL((rebisect_fp64_kernel<0, BATCH, COUNT>), dim3(cus * 2), dim3(256), 0,
+                       stream, single, table, sc.ctr + 2, sc.amb);
+  } else {
+    hipLaunchKernelGGL((refine_fp32_kernel<1, BATCH, COUNT>), dim3(rblocks), dim3(256), 0, stream,
+                       single, table, sc.ctr, sc.hits, sc.ctr + 2, sc.amb);
+    hipLaunchKernelGGL((rebisect_fp64_kernel<1, BATCH, COUNT>), dim3(cus * 2), dim3(256), 0,
+                       stream, single, table, sc.ctr + 2, sc.amb);
+  }
+}
+
+template <bool BATCH>
+static hipError_t launch_split_impl(const FrameDesc &single, const FrameDesc *table, int nframes,
+                                    uint32_t total_tiles, int norm, bool axis, bool count,
+                                    const SplitScratch &sc, const Sched &s, int cus,
+                                    hipStream_t stream) {
+  hipLaunchKernelGGL(reset_split_counters_kernel, dim3(1), dim3(64), 0, stream, sc.ctr);
+  if (count)
+    launch_split_variant<BATCH, true>(single, table, nframes, total_tiles, norm, axis, sc, s, cus,
+                                      stream);
+  else
+    launch_split_variant<BATCH, false>(single, table, nframes, total_tiles, norm, axis, sc, s, cus,
+                                       stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_split(const FrameDesc &frame, const SplitScratch &sc, const Sched &s,
+                               int cus, hipStream_t stream) {
+  return launch_split_impl<false>(frame, nullptr, 1, frame.ntiles, frame.P.norm,
+                                  frame.P.axis_slice != 0, frame.out.iters != nullptr, sc, s, cus,
+                                  stream);
+}
+
+hipError_t launch_render_split_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
+                                     int norm, bool all_axis, bool any_count,
+                                     const SplitScratch &sc, const Sched &s, int cus,
+                                     hipStream_t stream) {
+  FrameDesc dummy;
+  memset(&dummy, 0, sizeof dummy);
+  return launch_split_impl<true>(dummy, table_dev, nframes, total_tiles, norm, all_axis, any_count,
+                                 sc, s, cus, stream);
+}
+
+}  // namespace dqj
