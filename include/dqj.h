@@ -79,7 +79,7 @@ typedef struct dqj_params {
   int32_t max_iter;            /* N, 1..4096 */
   int32_t march_steps;         /* S >= 1: S+1 samples t_k = t0 + k (t1-t0)/S */
   int32_t bisect_steps;        /* B >= 0 (0..64) */
-  double escape_radius;        /* R > 0: escape iff ||z||^2 > R^2 */
+  double escape_radius;        /* R > 0: escape iff ||z||^2 > R^2 (SPLIT: R^2 < 65504) */
   int32_t norm;                /* DQJ_NORM_* */
   int32_t precision;           /* DQJ_PREC_* */
   int32_t fp64_window;         /* SPLIT only: FP32 verify window +-w samples (1..8), default 2 */

@@ -126,6 +126,8 @@ dqj_status validate_params(const dqj_params *p) {
     return fail(DQJ_E_INVALID, "precision must be one of DQJ_PREC_*");
   if (p->precision == DQJ_PREC_SPLIT && (p->fp64_window < 1 || p->fp64_window > 8))
     return fail(DQJ_E_INVALID, "fp64_window must be in 1..8 for split precision");
+  if (p->precision == DQJ_PREC_SPLIT && !(p->escape_radius * p->escape_radius < 65504.0))
+    return fail(DQJ_E_INVALID, "split precision needs escape_radius^2 < 65504 (FP16 range)");
   const double f[3] = {p->target[0] - p->eye[0], p->target[1] - p->eye[1], p->target[2] - p->eye[2]};
   const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
   if (!(fl > 0)) return fail(DQJ_E_INVALID, "eye and target coincide");

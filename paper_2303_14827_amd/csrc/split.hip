@@ -407,7 +407,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
             // enter as if the pair (-2, -1) had just escaped: the next trip starts pair 0
             kp = -2.0f;
             busy = true;
-            m2 = hsplat(65504.0f);
+            m2 = hsplat(INFINITY);
             z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = hsplat(0.0f);
             s = hsplat(0.0f);
             dl = trip + (uint32_t)N;
