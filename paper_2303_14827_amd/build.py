@@ -2,7 +2,10 @@
 
 Every .hip source under csrc/ is compiled with hipcc for gfx950 and linked into one
 shared library next to this file. Packed FP32 instructions are switched off for the
-device code (-packed-fp32-ops), so the compiler emits no v_pk_*_f32 forms.
+device code (-packed-fp32-ops), so the compiler emits no v_pk_*_f32 forms. FMA
+contraction is off: every fused multiply-add is written out, so each kernel
+instantiation rounds identically (batched, single-frame and served renders of one
+frame are bit-identical).
 """
 import glob
 import os
@@ -23,7 +26,7 @@ ARCH = "gfx950"
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast", "-fno-fast-math", "-Wall", "-Wno-unused-command-line-argument",
+    "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -129,7 +129,8 @@ template <typename T>
 __device__ __forceinline__ DQ<T> slice_map(const KParams &P, T x, T y, T z) {
   T v[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = T(P.so[k]) + x * T(P.su[k]) + y * T(P.sv[k]) + z * T(P.sw[k]);
+  for (int k = 0; k < 8; ++k)
+    v[k] = fma(z, T(P.sw[k]), fma(y, T(P.sv[k]), fma(x, T(P.su[k]), T(P.so[k]))));
   return DQ<T>{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
 }
 
@@ -139,8 +140,8 @@ __device__ __forceinline__ void pixel_dir(const KParams &P, int i, int j, float 
   const float sy = fmaf(-(float)(2 * j + 1), P.inv_h, 1.0f) * P.sy_scale;
   float v[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) v[k] = P.fwd[k] + sx * P.right[k] + sy * P.up[k];
-  const float inv = 1.0f / sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  for (int k = 0; k < 3; ++k) v[k] = fmaf(sy, P.up[k], fmaf(sx, P.right[k], P.fwd[k]));
+  const float inv = 1.0f / sqrtf(fmaf(v[2], v[2], fmaf(v[1], v[1], v[0] * v[0])));
   d[0] = v[0] * inv;
   d[1] = v[1] * inv;
   d[2] = v[2] * inv;

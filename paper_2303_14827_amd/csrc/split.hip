@@ -8,9 +8,11 @@
 //      The first inside FP16 sample k^ of each ray goes to a compacted hit list; rays
 //      with no inside sample are written as misses.
 //   2. refine_fp32: for each listed ray, classify the window k^-w .. k^+w in FP32. If the
-//      FP32 classes there are monotone (out ... out in ... in) and agree with FP16 at
-//      k^-1 and k^, bisect [t_{k^-1}, t_{k^}] in FP32, take the central-difference normal
-//      and shade. Otherwise the ray is ambiguous and goes to a second list.
+//      FP32 classes there are monotone (out ... out in ... in) with the change inside the
+//      window, the first FP32 inside sample k is the crossing: bisect [t_{k-1}, t_k] in
+//      FP32, take the central-difference normal and shade. Otherwise (the classes flip
+//      more than once, or all agree so the change lies outside the window) the ray is
+//      ambiguous and goes to a second list.
 //   3. rebisect_fp64: for each ambiguous ray, classify the window in FP64, take its first
 //      inside sample (marching on past the window in FP64 if there is none), then bisect,
 //      take the normal and shade in FP64.
@@ -34,6 +36,8 @@ struct DQH {
 
 __device__ __forceinline__ h2 hfma(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }
 __device__ __forceinline__ h2 hsplat(float v) { return h2{(_Float16)v, (_Float16)v}; }
+// Two FP32 values rounded to nearest FP16 and packed.
+__device__ __forceinline__ h2 hpack(float lo, float hi) { return h2{(_Float16)lo, (_Float16)hi}; }
 
 // One packed update of two independent points (one per half), as dq_update.
 template <int NORM>
@@ -97,10 +101,10 @@ __device__ __forceinline__ int find_frame(ConstFrame table, int nframes, uint32_
 
 // Pixel direction in FP64 (for the FP64 pass).
 __device__ __forceinline__ void pixel_dir64(const KParams64 &P, int i, int j, double d[3]) {
-  const double sx = ((double)(2 * i + 1) * P.inv_w - 1.0) * P.sx_scale;
-  const double sy = (1.0 - (double)(2 * j + 1) * P.inv_h) * P.sy_scale;
+  const double sx = fma((double)(2 * i + 1), P.inv_w, -1.0) * P.sx_scale;
+  const double sy = fma(-(double)(2 * j + 1), P.inv_h, 1.0) * P.sy_scale;
   double v[3];
-  for (int k = 0; k < 3; ++k) v[k] = P.fwd[k] + sx * P.right[k] + sy * P.up[k];
+  for (int k = 0; k < 3; ++k) v[k] = fma(sy, P.up[k], fma(sx, P.right[k], P.fwd[k]));
   const double inv = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   d[0] = v[0] * inv;
   d[1] = v[1] * inv;
@@ -136,7 +140,8 @@ template <typename P_T, typename T>
 __device__ __forceinline__ DQ<T> slice_map_t(const P_T &P, T x, T y, T z) {
   T v[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = T(P.so[k]) + x * T(P.su[k]) + y * T(P.sv[k]) + z * T(P.sw[k]);
+  for (int k = 0; k < 8; ++k)
+    v[k] = fma(z, T(P.sw[k]), fma(y, T(P.sv[k]), fma(x, T(P.su[k]), T(P.so[k]))));
   return DQ<T>{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
 }
 
@@ -293,9 +298,9 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
       }
       if (start) {
         const float tl = fmaf(kp, dt, t0), th = fmaf(kp + 1.0f, dt, t0);
-        const h2 xh = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fmaf(tl, dx, ex), fmaf(th, dx, ex)));
-        const h2 yh = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fmaf(tl, dy, ey), fmaf(th, dy, ey)));
-        const h2 wh = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fmaf(tl, dz, ez), fmaf(th, dz, ez)));
+        const h2 xh = hpack(fmaf(tl, dx, ex), fmaf(th, dx, ex));
+        const h2 yh = hpack(fmaf(tl, dy, ey), fmaf(th, dy, ey));
+        const h2 wh = hpack(fmaf(tl, dz, ez), fmaf(th, dz, ez));
         if (AXIS && closed_first) {
           // z_1 of (x, y, w, 0 | 0) in closed form; m2 starts at ||z_1||^2
           const h2 s0 = hfma(wh, wh, yh * yh);
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           const float wl = fmaf(tl, dz, ez), whh = fmaf(th, dz, ez);
           const DQ<float> zl = slice_map<float>(P, xl, yl, wl);
           const DQ<float> zh = slice_map<float>(P, xhh, yhh, whh);
-#define DQJ_PK(F_) __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(zl.F_, zh.F_))
+#define DQJ_PK(F_) hpack(zl.F_, zh.F_)
           z.a0 = DQJ_PK(a0);
           z.a1 = DQJ_PK(a1);
           z.a2 = DQJ_PK(a2);
@@ -464,15 +469,17 @@ __global__ __launch_bounds__(256) void refine_fp32_kernel(FrameDesc single,
       it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)k, dt, t0), d, 0.0f, 0.0f, 0.0f, &in, &n2);
       in_mask |= (in ? 1u : 0u) << (k - klo);
     }
-    // monotone: every bit above the lowest set bit is set (up to khi)
+    // The FP32 window decides the crossing when its classes are monotone
+    // (out ... out in ... in) with the change inside the window: an outside sample
+    // before the first inside one, or the first inside one is sample 0.
     const uint32_t full = (2u << (khi - klo)) - 1u;
     const uint32_t low = in_mask & (0u - in_mask);
     const bool monotone = in_mask != 0 && ((in_mask | (low - 1u)) == full);
-    const bool agree = ((in_mask >> (kh - klo)) & 1u) &&
-                       (kh == 0 || !((in_mask >> (kh - 1 - klo)) & 1u));
-    if (monotone && agree) {
+    const int kfirst = klo + (in_mask ? __builtin_ctz(in_mask) : 0);
+    const bool decided = monotone && (kfirst > klo || kfirst == 0);
+    if (decided) {
       PixelOut r;
-      it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, kh,
+      it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, kfirst,
                              (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
       write_pixel(F->out, en.pix, r);
     } else {
