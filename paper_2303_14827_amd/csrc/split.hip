@@ -14,8 +14,9 @@
 //      more than once, or all agree so the change lies outside the window) the ray is
 //      ambiguous and goes to a second list.
 //   3. rebisect_fp64: for each ambiguous ray, classify the window in FP64, take its first
-//      inside sample (marching on past the window in FP64 if there is none), then bisect,
-//      take the normal and shade in FP64.
+//      inside sample (marching on past the window in FP64 if there is none, and back to the
+//      start of the inside run if the window's first sample is already inside), then
+//      bisect, take the normal and shade in FP64.
 // The three kernels run back to back on one stream; list lengths stay on the device.
 #include <cstring>
 
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(256) void rebisect_fp64_kernel(FrameDesc single,
     } else {
       const double dt = (t1 - t0) / (double)S;
       const int w = F->P.fp64_window;
-      const int klo = en.khat - w > 0 ? en.khat - w : 0;
+      int klo = en.khat - w > 0 ? en.khat - w : 0;
       int kstar = -1;
       for (int k = klo; k <= S; ++k) {
         bool in;
@@ -529,6 +530,17 @@ __global__ __launch_bounds__(256) void rebisect_fp64_kernel(FrameDesc single,
           kstar = k;
           break;
         }
+      }
+      // The window starts inside: the FP16 march crossed late. Walk back to the start
+      // of this inside run (samples before an outside one are not re-checked).
+      while (kstar == klo && kstar > 0) {
+        bool in;
+        double n2;
+        it += classify_t<NORM>(Q, Q.c, N, Q.R2, fma((double)(kstar - 1), dt, t0), d, 0.0, 0.0, 0.0,
+                               &in, &n2);
+        if (!in) break;
+        --kstar;
+        --klo;
       }
       if (kstar < 0) {
         r = miss_pixel(DQJ_FLAG_BOX | DQJ_FLAG_FP64);
