@@ -156,6 +156,68 @@ dqj_status dqj_classify_points(const void *pts_dev, int32_t n, int32_t precision
                                const dqj_params *params, int32_t *escape_iter_dev,
                                float *final_norm2_dev, void *hip_stream);
 
+/* ---- Request server (continuous batching) -------------------------------------
+ * Requests of any size, Julia constant and max_iter are queued as they are
+ * submitted, admitted first come first served while the device bytes their
+ * framebuffers hold stay within the budget, and rendered in epochs: each epoch is
+ * one persistent launch (replayed from a HIP graph captured per epoch slot) over
+ * chunks of tiles taken from every active request, so work arriving while other
+ * requests run joins the next epoch and overlaps with them on the device. Up to
+ * `slots` epochs are in flight at once, each on its own stream. A request's result
+ * is bit-identical to a dqj_render of the same parameters and precision.
+ * Every dqj_serve_* call is thread-safe. */
+
+typedef struct dqj_serve_config {
+  uint32_t struct_size;        /* = sizeof(dqj_serve_config) */
+  uint64_t hbm_budget_bytes;   /* framebuffer bytes of admitted requests at once (0: 8 GiB) */
+  int32_t max_inflight;        /* admitted, unfinished requests at once (0: 64) */
+  int32_t max_pending;         /* queued requests before submit returns DQJ_E_QUEUE_FULL (0: 4096) */
+  int32_t precision;           /* DQJ_PREC_FP32 or DQJ_PREC_SPLIT; every request must match */
+  int32_t norm;                /* escape norm; every request must match */
+  int32_t slots;               /* epochs in flight at once, 1..8 (0: 3) */
+  int32_t count_iters;         /* 1: kernels add executed updates to each request's iters */
+  int64_t epoch_pixels;        /* pixels per epoch (0: 4 Mi); sizes the per-slot scratch */
+  double epoch_work;           /* estimated DQ updates per epoch (0: 2e9) */
+  dqj_schedule sched;          /* tile/wave schedule (struct_size 0: default) */
+} dqj_serve_config;
+
+typedef struct dqj_request_result {
+  uint32_t struct_size;        /* = sizeof(dqj_request_result) */
+  dqj_status status;           /* DQJ_PENDING until final: DQJ_OK, DQJ_E_CANCELLED, DQJ_E_DEVICE */
+  double t_submit, t_admit, t_first_launch, t_done;   /* host steady clock (s); -1 if not yet */
+  int32_t chunks;              /* launches the request's tiles were spread over */
+} dqj_request_result;
+
+typedef struct dqj_serve_stats {
+  uint32_t struct_size;        /* = sizeof(dqj_serve_stats) */
+  uint64_t submitted, admitted, completed, cancelled, failed, rejected, epochs;
+  int32_t pending, active;
+  uint64_t resident_bytes;
+  double p50_latency_s, p99_latency_s, max_latency_s, mean_latency_s;  /* t_done - t_submit */
+} dqj_serve_stats;
+
+typedef struct dqj_server dqj_server;   /* opaque, library-owned */
+
+/* Create a server on the current device (device memory for `slots` epochs is
+ * allocated here). */
+dqj_status dqj_serve_create(const dqj_serve_config *cfg, dqj_server **out);
+/* Validate and queue a request. out holds caller-owned device buffers that must stay
+ * valid until the request is final. DQJ_E_INVALID, DQJ_E_BUDGET (its framebuffer
+ * bytes alone exceed the budget), DQJ_E_QUEUE_FULL, DQJ_E_STATE (server closing). */
+dqj_status dqj_serve_submit(dqj_server *s, const dqj_params *params, const dqj_frame_out *out,
+                            uint64_t *ticket);
+/* DQJ_PENDING, or the request's final status; fills *res either way. */
+dqj_status dqj_serve_poll(dqj_server *s, uint64_t ticket, dqj_request_result *res);
+/* Wait up to timeout_ms (< 0: no limit) for the request to be final: its final
+ * status, or DQJ_E_TIMEOUT (the request keeps running). */
+dqj_status dqj_serve_wait(dqj_server *s, uint64_t ticket, int32_t timeout_ms,
+                          dqj_request_result *res);
+/* Cancel a pending or running request (its tiles already launched still finish). */
+dqj_status dqj_serve_cancel(dqj_server *s, uint64_t ticket);
+dqj_status dqj_serve_stats_get(dqj_server *s, dqj_serve_stats *out);
+/* Cancel pending requests, wait for epochs in flight, free everything. */
+dqj_status dqj_serve_destroy(dqj_server *s);
+
 typedef struct dqj_device_info {
   uint32_t struct_size;
   char arch[64];               /* e.g. "gfx950:sramecc+:xnack-" */

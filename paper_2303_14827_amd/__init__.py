@@ -83,6 +83,54 @@ class dqj_schedule(C.Structure):
     ]
 
 
+class dqj_serve_config(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("hbm_budget_bytes", C.c_uint64),
+        ("max_inflight", C.c_int32),
+        ("max_pending", C.c_int32),
+        ("precision", C.c_int32),
+        ("norm", C.c_int32),
+        ("slots", C.c_int32),
+        ("count_iters", C.c_int32),
+        ("epoch_pixels", C.c_int64),
+        ("epoch_work", C.c_double),
+        ("sched", dqj_schedule),
+    ]
+
+
+class dqj_request_result(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("status", C.c_int32),
+        ("t_submit", C.c_double),
+        ("t_admit", C.c_double),
+        ("t_first_launch", C.c_double),
+        ("t_done", C.c_double),
+        ("chunks", C.c_int32),
+    ]
+
+
+class dqj_serve_stats(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("submitted", C.c_uint64),
+        ("admitted", C.c_uint64),
+        ("completed", C.c_uint64),
+        ("cancelled", C.c_uint64),
+        ("failed", C.c_uint64),
+        ("rejected", C.c_uint64),
+        ("epochs", C.c_uint64),
+        ("pending", C.c_int32),
+        ("active", C.c_int32),
+        ("resident_bytes", C.c_uint64),
+        ("p50_latency_s", C.c_double),
+        ("p99_latency_s", C.c_double),
+        ("max_latency_s", C.c_double),
+        ("mean_latency_s", C.c_double),
+    ]
+
+
 class dqj_device_info(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32),
@@ -113,6 +161,15 @@ _SIGS = {
     "dqj_classify_points": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(dqj_params),
                                         C.c_void_p, C.c_void_p, C.c_void_p]),
     "dqj_device_info_get": (C.c_int32, [C.c_int32, C.POINTER(dqj_device_info)]),
+    "dqj_serve_create": (C.c_int32, [C.POINTER(dqj_serve_config), C.POINTER(C.c_void_p)]),
+    "dqj_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(dqj_params), C.POINTER(dqj_frame_out),
+                                     C.POINTER(C.c_uint64)]),
+    "dqj_serve_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(dqj_request_result)]),
+    "dqj_serve_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32,
+                                   C.POINTER(dqj_request_result)]),
+    "dqj_serve_cancel": (C.c_int32, [C.c_void_p, C.c_uint64]),
+    "dqj_serve_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(dqj_serve_stats)]),
+    "dqj_serve_destroy": (C.c_int32, [C.c_void_p]),
     "dqj_last_error": (C.c_char_p, []),
     "dqj_status_str": (C.c_char_p, [C.c_int32]),
 }
@@ -278,6 +335,104 @@ def classify_points(pts, p, precision: int = PREC_FP32, stream=None):
                                      C.c_void_p(esc.data_ptr()), C.c_void_p(n2.data_ptr()),
                                      _stream(stream)))
     return esc, n2
+
+
+def _result_dict(r: dqj_request_result) -> Dict:
+    return {"status": r.status, "t_submit": r.t_submit, "t_admit": r.t_admit,
+            "t_first_launch": r.t_first_launch, "t_done": r.t_done, "chunks": r.chunks}
+
+
+class Server:
+    """The library's request server (continuous batching over epoch slots).
+
+    submit() takes a Params-like record and a dict of caller-owned device tensors
+    (alloc_outputs); the tensors must stay alive until the request is final.
+    """
+
+    def __init__(self, precision: int = PREC_SPLIT, norm: int = NORM_EUCLID8,
+                 hbm_budget_bytes: int = 0, max_inflight: int = 0, max_pending: int = 0,
+                 slots: int = 0, epoch_pixels: int = 0, epoch_work: float = 0.0,
+                 count_iters: bool = False, schedule: Optional[dqj_schedule] = None):
+        cfg = dqj_serve_config()
+        cfg.struct_size = C.sizeof(dqj_serve_config)
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        cfg.max_inflight, cfg.max_pending = max_inflight, max_pending
+        cfg.precision, cfg.norm, cfg.slots = precision, norm, slots
+        cfg.count_iters = 1 if count_iters else 0
+        cfg.epoch_pixels, cfg.epoch_work = epoch_pixels, epoch_work
+        if schedule is not None:
+            cfg.sched = schedule
+        h = C.c_void_p()
+        _check(lib().dqj_serve_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, p, out: Dict) -> int:
+        sp = make_params(p)
+        fo = make_frame_out(out)
+        t = C.c_uint64()
+        _check(lib().dqj_serve_submit(self._h, C.byref(sp), C.byref(fo), C.byref(t)))
+        self._keep[t.value] = out
+        return t.value
+
+    def submit_status(self, p, out: Dict):
+        """(status, ticket) without raising: for tests of refusals."""
+        sp = make_params(p)
+        fo = make_frame_out(out)
+        t = C.c_uint64()
+        st = lib().dqj_serve_submit(self._h, C.byref(sp), C.byref(fo), C.byref(t))
+        if st == OK:
+            self._keep[t.value] = out
+        return st, t.value
+
+    def poll(self, ticket: int):
+        r = dqj_request_result()
+        r.struct_size = C.sizeof(dqj_request_result)
+        st = lib().dqj_serve_poll(self._h, ticket, C.byref(r))
+        if st == E_INVALID:
+            _check(st)
+        d = _result_dict(r)
+        d["status"] = st
+        return d
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        r = dqj_request_result()
+        r.struct_size = C.sizeof(dqj_request_result)
+        st = lib().dqj_serve_wait(self._h, ticket, timeout_ms, C.byref(r))
+        if st == E_INVALID:
+            _check(st)
+        d = _result_dict(r)
+        d["status"] = st
+        if st not in (PENDING, E_TIMEOUT):
+            self._keep.pop(ticket, None)
+        return d
+
+    def cancel(self, ticket: int) -> int:
+        return lib().dqj_serve_cancel(self._h, ticket)
+
+    def stats(self) -> Dict:
+        s = dqj_serve_stats()
+        s.struct_size = C.sizeof(dqj_serve_stats)
+        _check(lib().dqj_serve_stats_get(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in dqj_serve_stats._fields_ if k != "struct_size"}
+
+    def close(self):
+        if self._h:
+            _check(lib().dqj_serve_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_info(device: int = 0) -> Dict:

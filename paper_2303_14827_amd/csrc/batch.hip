@@ -156,13 +156,13 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
       uint32_t *counter = nullptr;
       if (e == hipSuccess) e = stream_counter(stream, &counter);
       if (e == hipSuccess)
-        e = launch_render_refill_batch((const FrameDesc *)r.dev, n, total, norm, all_axis,
+        e = launch_render_refill_batch((const FrameDesc *)r.dev, nullptr, n, total, norm, all_axis,
                                        any_count, counter, s, cus, stream);
     } else {
       void *scratch = nullptr;
       if (e == hipSuccess) e = stream_scratch(stream, split_scratch_bytes(pixels), &scratch);
       if (e == hipSuccess)
-        e = launch_render_split_batch((const FrameDesc *)r.dev, n, total, norm, all_axis, any_count,
+        e = launch_render_split_batch((const FrameDesc *)r.dev, nullptr, n, total, norm, all_axis, any_count,
                                       split_scratch_at(scratch, pixels), s, cus, stream);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ev, hipEventDisableTiming);
@@ -228,9 +228,9 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
       // The capture holds a counter-reset kernel (not a memset node) and the kernel.
       hipError_t le =
           precision == DQJ_PREC_FP32
-              ? launch_render_refill_batch(p->table_dev, n, total, norm, all_axis, any_count,
+              ? launch_render_refill_batch(p->table_dev, nullptr, n, total, norm, all_axis, any_count,
                                            p->counter_dev, s, cus, p->cap_stream)
-              : launch_render_split_batch(p->table_dev, n, total, norm, all_axis, any_count,
+              : launch_render_split_batch(p->table_dev, nullptr, n, total, norm, all_axis, any_count,
                                           split_scratch_at(p->split_scratch, pixels), s, cus,
                                           p->cap_stream);
       e = hipStreamEndCapture(p->cap_stream, &p->graph);

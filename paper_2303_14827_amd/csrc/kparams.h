@@ -63,14 +63,24 @@ struct KOut {
 
 // One frame of a (possibly single-frame) persistent launch: its parameters, its
 // outputs, and where its tiles sit in the launch's global tile sequence.
+// An entry may cover a chunk of a frame's tiles: tiles tile_offset .. tile_offset +
+// ntiles - 1 of the frame (a served request split across several launches).
 struct alignas(16) FrameDesc {
   KParams P;
   KParams64 P64;
   KOut out;
-  uint32_t tile_begin;   // first global tile index of this frame
+  uint32_t tile_begin;   // first global tile index of this entry in the launch
   uint32_t tiles_x;      // tiles per image row
-  uint32_t ntiles;       // tiles of this frame
-  uint32_t pad;
+  uint32_t ntiles;       // tiles of this entry
+  uint32_t tile_offset;  // frame tile of this entry's first tile
+};
+
+// Device header a launch may read its size from (so one captured graph serves any
+// table contents): [0] number of entries, [1] total tiles.
+struct LaunchHeader {
+  uint32_t nframes;
+  uint32_t total_tiles;
+  uint32_t pad[62];
 };
 
 }  // namespace dqj

@@ -13,9 +13,11 @@ hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const
 
 // n frames from a device-resident table; all frames share norm; all_axis is true only
 // if every frame uses the identity slice.
-hipError_t launch_render_refill_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
-                                      int norm, bool all_axis, bool any_count, uint32_t *counter,
-                                      const Sched &s, int cus, hipStream_t stream);
+// hdr_dev (may be null) overrides nframes/total_tiles with values read on the device.
+hipError_t launch_render_refill_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
+                                      int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                      bool any_count, uint32_t *counter, const Sched &s, int cus,
+                                      hipStream_t stream);
 
 // Fill the tile geometry of a frame descriptor (tile_begin must be set by the caller).
 inline void set_tiles(FrameDesc &f, int tw, int th) {

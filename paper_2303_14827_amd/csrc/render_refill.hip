@@ -52,8 +52,10 @@ __device__ __forceinline__ float uniform_f(float v) {
 // of the compiler only needs the type to exist.)
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef const __attribute__((address_space(4))) FrameDesc *ConstFrame;
+typedef const __attribute__((address_space(4))) LaunchHeader *ConstHeader;
 #else
 typedef const FrameDesc *ConstFrame;
+typedef const LaunchHeader *ConstHeader;
 #endif
 
 template <bool BATCH>
@@ -96,11 +98,18 @@ __device__ __forceinline__ void start_point(const KParams &P, float x, float y, 
 template <int NORM, bool AXIS, bool BATCH, bool COUNT>
 __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
                                                              const FrameDesc *__restrict__ table,
+                                                             const LaunchHeader *__restrict__ hdr,
                                                              int nframes, uint32_t total_tiles,
                                                              uint32_t *__restrict__ counter,
                                                              int TW, int TH) {
   const int lane = lane_id();
   const int tile_rays = TW * TH;
+  if constexpr (BATCH) {
+    if (hdr) {   // sizes of this launch from device memory (graph replays with new tables)
+      nframes = (int)uniform(((ConstHeader)hdr)->nframes);
+      total_tiles = uniform(((ConstHeader)hdr)->total_tiles);
+    }
+  }
   const float kNaN = __builtin_nanf("");
   const float kNoMarch = 1e30f;   // k outside the march: the fast-path test k < S fails
 
@@ -316,7 +325,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
                            : 0.0f;
           closed_first = AXIS && N > 1;
         }
-        tile_local = pend_tile - F->tile_begin;
+        tile_local = pend_tile - F->tile_begin + F->tile_offset;
         pending = false;
         have_tile = true;
         next_r = 0;
@@ -366,12 +375,13 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
 template <bool BATCH, bool COUNT>
-static void launch_refill_variant(const FrameDesc &single, const FrameDesc *table, int nframes,
+static void launch_refill_variant(const FrameDesc &single, const FrameDesc *table,
+                                  const LaunchHeader *hdr, int nframes,
                                   uint32_t total_tiles, int norm, bool axis, uint32_t *counter,
                                   const Sched &s, int blocks, int threads, hipStream_t stream) {
 #define DQJ_LAUNCH(NM, AX)                                                                    \
   hipLaunchKernelGGL((render_refill_kernel<NM, AX, BATCH, COUNT>), dim3(blocks), dim3(threads), \
-                     0, stream, single, table, nframes, total_tiles, counter, s.tile_w, s.tile_h)
+                     0, stream, single, table, hdr, nframes, total_tiles, counter, s.tile_w, s.tile_h)
   if (norm == 0) {
     if (axis)
       DQJ_LAUNCH(0, true);
@@ -387,7 +397,8 @@ static void launch_refill_variant(const FrameDesc &single, const FrameDesc *tabl
 }
 
 template <bool BATCH>
-static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *table, int nframes,
+static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *table,
+                                     const LaunchHeader *hdr, int nframes,
                                      uint32_t total_tiles, int norm, bool axis, bool count,
                                      uint32_t *counter, const Sched &s, int cus,
                                      hipStream_t stream) {
@@ -395,28 +406,29 @@ static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *t
   const int threads = 64 * s.waves_per_block;
   const int blocks = cus * s.blocks_per_cu;
   if (count)
-    launch_refill_variant<BATCH, true>(single, table, nframes, total_tiles, norm, axis, counter, s,
-                                       blocks, threads, stream);
+    launch_refill_variant<BATCH, true>(single, table, hdr, nframes, total_tiles, norm, axis, counter,
+                                       s, blocks, threads, stream);
   else
-    launch_refill_variant<BATCH, false>(single, table, nframes, total_tiles, norm, axis, counter, s,
-                                        blocks, threads, stream);
+    launch_refill_variant<BATCH, false>(single, table, hdr, nframes, total_tiles, norm, axis, counter,
+                                        s, blocks, threads, stream);
   return hipGetLastError();
 }
 
 hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
                                 hipStream_t stream) {
-  return launch_refill_impl<false>(frame, nullptr, 1, frame.ntiles, frame.P.norm,
+  return launch_refill_impl<false>(frame, nullptr, nullptr, 1, frame.ntiles, frame.P.norm,
                                    frame.P.axis_slice != 0, frame.out.iters != nullptr, counter, s,
                                    cus, stream);
 }
 
-hipError_t launch_render_refill_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
-                                      int norm, bool all_axis, bool any_count, uint32_t *counter,
-                                      const Sched &s, int cus, hipStream_t stream) {
+hipError_t launch_render_refill_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
+                                      int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                      bool any_count, uint32_t *counter, const Sched &s, int cus,
+                                      hipStream_t stream) {
   FrameDesc dummy;
   memset(&dummy, 0, sizeof dummy);
-  return launch_refill_impl<true>(dummy, table_dev, nframes, total_tiles, norm, all_axis, any_count,
-                                  counter, s, cus, stream);
+  return launch_refill_impl<true>(dummy, table_dev, hdr_dev, nframes, total_tiles, norm, all_axis,
+                                  any_count, counter, s, cus, stream);
 }
 
 }  // namespace dqj

@@ -38,9 +38,10 @@ inline SplitScratch split_scratch_at(void *base, uint64_t pixels) {
 
 hipError_t launch_render_split(const FrameDesc &frame, const SplitScratch &sc, const Sched &s,
                                int cus, hipStream_t stream);
-hipError_t launch_render_split_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
-                                     int norm, bool all_axis, bool any_count,
-                                     const SplitScratch &sc, const Sched &s, int cus,
+// hdr_dev (may be null) overrides nframes/total_tiles with values read on the device.
+hipError_t launch_render_split_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
+                                     int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                     bool any_count, const SplitScratch &sc, const Sched &s, int cus,
                                      hipStream_t stream);
 
 }  // namespace dqj

@@ -75,8 +75,10 @@ __device__ __forceinline__ float uniform_f(float v) {
 
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef const __attribute__((address_space(4))) FrameDesc *ConstFrame;
+typedef const __attribute__((address_space(4))) LaunchHeader *ConstHeader;
 #else
 typedef const FrameDesc *ConstFrame;
+typedef const LaunchHeader *ConstHeader;
 #endif
 
 template <bool BATCH>
@@ -232,12 +234,19 @@ __device__ __forceinline__ uint32_t finish_ray(const P_T &P, const T *c, int N, 
 template <int NORM, bool AXIS, bool BATCH, bool COUNT>
 __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
                                                           const FrameDesc *__restrict__ table,
+                                                          const LaunchHeader *__restrict__ hdr,
                                                           int nframes, uint32_t total_tiles,
                                                           uint32_t *__restrict__ ctr,
                                                           SplitEntry *__restrict__ hits, int TW,
                                                           int TH) {
   const int lane = lane_id();
   const int tile_rays = TW * TH;
+  if constexpr (BATCH) {
+    if (hdr) {   // sizes of this launch from device memory (graph replays with new tables)
+      nframes = (int)uniform(((ConstHeader)hdr)->nframes);
+      total_tiles = uniform(((ConstHeader)hdr)->total_tiles);
+    }
+  }
   const ConstFrame ctable = (ConstFrame)table;
   typename FramePtr<BATCH>::type F;
   if constexpr (BATCH)
@@ -387,7 +396,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           cdsq = hsplat(NORM == 0 ? cf[4] * cf[4] + cf[5] * cf[5] + cf[6] * cf[6] + cf[7] * cf[7] : 0.0f);
           closed_first = AXIS && N > 1;
         }
-        tile_local = pend_tile - F->tile_begin;
+        tile_local = pend_tile - F->tile_begin + F->tile_offset;
         pending = false;
         have_tile = true;
         next_r = 0;
@@ -559,14 +568,15 @@ __global__ void reset_split_counters_kernel(uint32_t *ctr) {
 }
 
 template <bool BATCH, bool COUNT>
-static void launch_split_variant(const FrameDesc &single, const FrameDesc *table, int nframes,
+static void launch_split_variant(const FrameDesc &single, const FrameDesc *table,
+                                 const LaunchHeader *hdr, int nframes,
                                  uint32_t total_tiles, int norm, bool axis, const SplitScratch &sc,
                                  const Sched &s, int cus, hipStream_t stream) {
   const int threads = 64 * s.waves_per_block;
   const int blocks = cus * s.blocks_per_cu;
 #define DQJ_MARCH(NM, AX)                                                                     \
   hipLaunchKernelGGL((march_fp16_kernel<NM, AX, BATCH, COUNT>), dim3(blocks), dim3(threads), 0, \
-                     stream, single, table, nframes, total_tiles, sc.ctr, sc.hits, s.tile_w,     \
+                     stream, single, table, hdr, nframes, total_tiles, sc.ctr, sc.hits, s.tile_w, \
                      s.tile_h)
   if (norm == 0) {
     if (axis)
@@ -595,35 +605,36 @@ static void launch_split_variant(const FrameDesc &single, const FrameDesc *table
 }
 
 template <bool BATCH>
-static hipError_t launch_split_impl(const FrameDesc &single, const FrameDesc *table, int nframes,
+static hipError_t launch_split_impl(const FrameDesc &single, const FrameDesc *table,
+                                    const LaunchHeader *hdr, int nframes,
                                     uint32_t total_tiles, int norm, bool axis, bool count,
                                     const SplitScratch &sc, const Sched &s, int cus,
                                     hipStream_t stream) {
   hipLaunchKernelGGL(reset_split_counters_kernel, dim3(1), dim3(64), 0, stream, sc.ctr);
   if (count)
-    launch_split_variant<BATCH, true>(single, table, nframes, total_tiles, norm, axis, sc, s, cus,
-                                      stream);
+    launch_split_variant<BATCH, true>(single, table, hdr, nframes, total_tiles, norm, axis, sc, s,
+                                      cus, stream);
   else
-    launch_split_variant<BATCH, false>(single, table, nframes, total_tiles, norm, axis, sc, s, cus,
-                                       stream);
+    launch_split_variant<BATCH, false>(single, table, hdr, nframes, total_tiles, norm, axis, sc, s,
+                                       cus, stream);
   return hipGetLastError();
 }
 
 hipError_t launch_render_split(const FrameDesc &frame, const SplitScratch &sc, const Sched &s,
                                int cus, hipStream_t stream) {
-  return launch_split_impl<false>(frame, nullptr, 1, frame.ntiles, frame.P.norm,
+  return launch_split_impl<false>(frame, nullptr, nullptr, 1, frame.ntiles, frame.P.norm,
                                   frame.P.axis_slice != 0, frame.out.iters != nullptr, sc, s, cus,
                                   stream);
 }
 
-hipError_t launch_render_split_batch(const FrameDesc *table_dev, int nframes, uint32_t total_tiles,
-                                     int norm, bool all_axis, bool any_count,
-                                     const SplitScratch &sc, const Sched &s, int cus,
+hipError_t launch_render_split_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
+                                     int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                     bool any_count, const SplitScratch &sc, const Sched &s, int cus,
                                      hipStream_t stream) {
   FrameDesc dummy;
   memset(&dummy, 0, sizeof dummy);
-  return launch_split_impl<true>(dummy, table_dev, nframes, total_tiles, norm, all_axis, any_count,
-                                 sc, s, cus, stream);
+  return launch_split_impl<true>(dummy, table_dev, hdr_dev, nframes, total_tiles, norm, all_axis,
+                                 any_count, sc, s, cus, stream);
 }
 
 }  // namespace dqj

@@ -33,15 +33,18 @@ def test_library_exports_every_declared_function():
 
 def test_record_sizes_match_header(tmp_path):
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "dqj.h"\nint main(void){printf("%zu %zu %zu %zu\\n",'
+    src.write_text('#include <stdio.h>\n#include "dqj.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
                    'sizeof(dqj_params), sizeof(dqj_frame_out), sizeof(dqj_schedule),'
-                   'sizeof(dqj_device_info)); return 0;}\n')
+                   'sizeof(dqj_device_info), sizeof(dqj_serve_config), sizeof(dqj_request_result),'
+                   'sizeof(dqj_serve_stats)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     sizes = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                             check=True).stdout.split()]
     assert sizes == [C.sizeof(dqj.dqj_params), C.sizeof(dqj.dqj_frame_out),
-                     C.sizeof(dqj.dqj_schedule), C.sizeof(dqj.dqj_device_info)]
+                     C.sizeof(dqj.dqj_schedule), C.sizeof(dqj.dqj_device_info),
+                     C.sizeof(dqj.dqj_serve_config), C.sizeof(dqj.dqj_request_result),
+                     C.sizeof(dqj.dqj_serve_stats)]
 
 
 def _render_status(p, **out_overrides):

@@ -9,9 +9,6 @@ before the FP32 window, are not re-checked, so >= 99.5 % of pixels must agree an
 within one march step of the set's boundary, and depth on agreeing hits within
 1e-4 of the box diagonal.
 """
-
-SPLIT_MIN_AGREE = 0.995
-SPLIT_SHADE_FRAC = 0.995
 import sys
 
 import numpy as np
@@ -19,6 +16,9 @@ import pytest
 
 import workloads
 from parity import assert_parity, compare, to_numpy
+
+SPLIT_MIN_AGREE = 0.995
+SPLIT_SHADE_FRAC = 0.995
 
 pytestmark = pytest.mark.gpu
 
