@@ -58,6 +58,111 @@ def cpu_baseline(ps, target_s):
             "seconds": round(dt, 2)}
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.quantile(np.asarray(xs), q)) if len(xs) else None
+
+
+def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
+    """The request stream replayed against the server (split precision, continuous
+    batching) and against the plain path (one FP32 dqj_render at a time, FIFO).
+
+    Open loop: requests are submitted at their scheduled (Poisson) arrival times;
+    latency = completion seen by the host - scheduled arrival. Closed loop
+    ("capacity"): the first capacity_n requests submitted back to back; throughput =
+    requests, pixels and GPU-counted DQ updates over the makespan.
+    """
+    import threading
+    import queue as q
+
+    stream = workloads.serve_stream(duration_s=duration_s, rate_hz=rate_hz)
+
+    def served(arrivals, open_loop):
+        srv = dqj.Server(precision=workloads.PREC_SPLIT, count_iters=True)
+        pend = q.Queue()
+        t0 = time.monotonic() + 0.05
+
+        def submitter():
+            for a in arrivals:
+                if open_loop:
+                    dt = t0 + a.t - time.monotonic()
+                    if dt > 0:
+                        time.sleep(dt)
+                out = dqj.alloc_outputs(a.params.width, a.params.height, extras=False)
+                tk = srv.submit(a.params, out)
+                pend.put((tk, (t0 + a.t) if open_loop else time.monotonic(), out, a.params))
+            pend.put(None)
+
+        th = threading.Thread(target=submitter)
+        start = time.monotonic()
+        th.start()
+        lats, iters, pixels, n = [], 0, 0, 0
+        while True:
+            item = pend.get()
+            if item is None:
+                break
+            tk, t_arr, out, p = item
+            r = srv.wait(tk)
+            assert r["status"] == dqj.OK, r
+            lats.append(r["t_done"] - t_arr)
+            iters += int(out["iters"].item())
+            pixels += p.pixels
+            n += 1
+        th.join()
+        end = time.monotonic()
+        st = srv.stats()
+        srv.close()
+        return lats, iters, pixels, n, end - start, st
+
+    def plain(arrivals, open_loop):
+        s = torch.cuda.current_stream()
+        t0 = time.monotonic() + 0.05
+        lats, iters, pixels = [], 0, 0
+        start = time.monotonic()
+        for a in arrivals:
+            p = a.params.replace(precision=workloads.PREC_FP32)
+            if open_loop:
+                dt = t0 + a.t - time.monotonic()
+                if dt > 0:
+                    time.sleep(dt)
+                t_arr = t0 + a.t
+            else:
+                t_arr = time.monotonic()
+            out = dqj.alloc_outputs(p.width, p.height, extras=False)
+            dqj.render(p, out=out, stream=s)
+            s.synchronize()
+            lats.append(time.monotonic() - t_arr)
+            iters += int(out["iters"].item())
+            pixels += p.pixels
+        return lats, iters, pixels, len(arrivals), time.monotonic() - start
+
+    res = {"stream": f"Poisson {rate_hz:g} req/s for {duration_s:g} s ({len(stream)} requests), "
+                     "side uniform over {128,256,512,1024,2048}, max_iter U[8,64], "
+                     "march steps 16*max_iter, 10 bisection steps",
+           "requests": len(stream)}
+    sl, si, sp, sn, sdur, sst = served(stream, True)
+    res["served"] = {"precision": "split (FP16 march, FP32 bisection, FP64 re-bisection)",
+                     "p50_ms": 1e3 * _pct(sl, 0.5), "p99_ms": 1e3 * _pct(sl, 0.99),
+                     "max_ms": 1e3 * max(sl), "epochs": sst["epochs"]}
+    pl, pi, pp, pn, pdur = plain(stream, True)
+    res["plain"] = {"precision": "FP32, one request at a time, FIFO",
+                    "p50_ms": 1e3 * _pct(pl, 0.5), "p99_ms": 1e3 * _pct(pl, 0.99),
+                    "max_ms": 1e3 * max(pl)}
+    cap = stream[:capacity_n]
+    cl, ci, cp, cn, cdur, _ = served(cap, False)
+    ql, qi, qp, qn, qdur = plain(cap, False)
+    res["capacity"] = {
+        "requests": cn,
+        "served": {"req_per_s": cn / cdur, "mpix_per_s": cp / cdur / 1e6,
+                   "iters_per_s": ci / cdur, "makespan_s": cdur},
+        "plain": {"req_per_s": qn / qdur, "mpix_per_s": qp / qdur / 1e6,
+                  "iters_per_s": qi / qdur, "makespan_s": qdur},
+        "note": "iters = DQ updates counted on the GPU (split: FP16 march through the first "
+                "inside sample + FP32 window/bisection/normal + FP64 re-bisection; plain: "
+                "the method's count in FP32)"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +171,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel", choices=["refill", "direct"], default="refill")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the served request stream (0: skip; the full stream is 60)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--capacity-requests", type=int, default=300)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -171,6 +280,9 @@ def main():
         "device": {"arch": info["arch"], "cus": info["compute_units"],
                    "clock_mhz": info["clock_khz"] / 1000.0},
     }
+    if args.serve_seconds > 0:
+        line["serve"] = serve_bench(args.serve_seconds, args.serve_rate, args.capacity_requests,
+                                    dqj, workloads, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
     if args.kernel == "refill":

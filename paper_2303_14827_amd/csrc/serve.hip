@@ -201,7 +201,7 @@ void scheduler_loop(dqj_server *s) {
       s->cv_sched.wait_for(lk, std::chrono::microseconds(50));
     else
       s->cv_sched.wait(lk, [&] { return s->stop || s->core.has_unassigned() ||
-                                        s->core.stats().pending > 0; });
+                                        s->core.pending_count() > 0; });
   }
   s->cv_done.notify_all();
 }

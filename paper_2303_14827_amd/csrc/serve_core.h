@@ -104,6 +104,7 @@ class Core {
   const RequestInfo *info(uint64_t ticket) const;
   CoreStats stats() const;
   bool idle() const { return pending_.empty() && active_.empty(); }
+  size_t pending_count() const { return pending_.size(); }
   bool has_unassigned() const;
 
  private:
