@@ -83,12 +83,14 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
         t0 = time.monotonic() + 0.05
 
         def submitter():
+            cur = torch.cuda.current_stream()
             for a in arrivals:
                 if open_loop:
                     dt = t0 + a.t - time.monotonic()
                     if dt > 0:
                         time.sleep(dt)
                 out = dqj.alloc_outputs(a.params.width, a.params.height, extras=False)
+                cur.synchronize()   # the zeroed work counter must be in place before the server adds to it
                 tk = srv.submit(a.params, out)
                 pend.put((tk, (t0 + a.t) if open_loop else time.monotonic(), out, a.params))
             pend.put(None)
@@ -96,7 +98,7 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
         th = threading.Thread(target=submitter)
         start = time.monotonic()
         th.start()
-        lats, iters, pixels, n = [], 0, 0, 0
+        lats, counters, pixels, n = [], [], 0, 0
         while True:
             item = pend.get()
             if item is None:
@@ -105,11 +107,12 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
             r = srv.wait(tk)
             assert r["status"] == dqj.OK, r
             lats.append(r["t_done"] - t_arr)
-            iters += int(out["iters"].item())
+            counters.append(out["iters"])   # summed once at the end, off the critical path
             pixels += p.pixels
             n += 1
         th.join()
         end = time.monotonic()
+        iters = int(torch.stack(counters).sum().item())
         st = srv.stats()
         srv.close()
         return lats, iters, pixels, n, end - start, st
@@ -117,7 +120,7 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
     def plain(arrivals, open_loop):
         s = torch.cuda.current_stream()
         t0 = time.monotonic() + 0.05
-        lats, iters, pixels = [], 0, 0
+        lats, counters, pixels = [], [], 0
         start = time.monotonic()
         for a in arrivals:
             p = a.params.replace(precision=workloads.PREC_FP32)
@@ -132,9 +135,10 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
             dqj.render(p, out=out, stream=s)
             s.synchronize()
             lats.append(time.monotonic() - t_arr)
-            iters += int(out["iters"].item())
+            counters.append(out["iters"])
             pixels += p.pixels
-        return lats, iters, pixels, len(arrivals), time.monotonic() - start
+        dur = time.monotonic() - start
+        return lats, int(torch.stack(counters).sum().item()), pixels, len(arrivals), dur
 
     res = {"stream": f"Poisson {rate_hz:g} req/s for {duration_s:g} s ({len(stream)} requests), "
                      "side uniform over {128,256,512,1024,2048}, max_iter U[8,64], "

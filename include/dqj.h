@@ -177,7 +177,7 @@ typedef struct dqj_serve_config {
   int32_t slots;               /* epochs in flight at once, 1..8 (0: 3) */
   int32_t count_iters;         /* 1: kernels add executed updates to each request's iters */
   int64_t epoch_pixels;        /* pixels per epoch (0: 4 Mi); sizes the per-slot scratch */
-  double epoch_work;           /* estimated DQ updates per epoch (0: 2e9) */
+  double epoch_work;           /* estimated DQ updates per epoch (0: 8e9) */
   dqj_schedule sched;          /* tile/wave schedule (struct_size 0: default) */
 } dqj_serve_config;
 

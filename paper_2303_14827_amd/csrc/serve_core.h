@@ -35,7 +35,7 @@ struct CoreConfig {
   uint64_t budget_bytes = 8ull << 30;  // resident bytes of admitted requests at once
   int32_t max_inflight = 64;           // admitted, unfinished requests at once
   int32_t max_pending = 4096;          // queue length before submit is refused
-  double epoch_work = 2e9;             // estimated DQ updates per epoch
+  double epoch_work = 8e9;             // estimated DQ updates per epoch
   uint64_t epoch_pixels = 4u << 20;    // pixels per epoch (scratch capacity)
   int32_t max_chunks = 256;            // table entries per epoch
 };
