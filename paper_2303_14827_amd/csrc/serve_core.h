@@ -11,6 +11,7 @@
 // Times are host steady-clock seconds supplied by the caller, so the core can be
 // driven by a simulated clock in tests.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 #include <deque>
 #include <unordered_map>
