@@ -134,7 +134,18 @@ typedef struct dqj_schedule {
   int32_t blocks_per_cu;       /* persistent grid = CUs * blocks_per_cu, 1..32 */
 } dqj_schedule;
 
-/* dqj_render with an explicit schedule (NULL = default). */
+/* Time each candidate schedule on the given representative frames (rendered into
+ * outs as one batched launch per candidate, so outs are overwritten) and remember
+ * the fastest for this workload shape (image size, max_iter, march and bisection
+ * steps, precision, norm, slice kind, device). Renders and plans created later
+ * without an explicit schedule use it. If cache_path (or the environment variable
+ * DQJ_TUNE_CACHE) names a file, the choice is appended to it as a JSON line and the
+ * file is read at the first schedule lookup of a later process. best (may be NULL)
+ * receives the choice. Synchronous. */
+dqj_status dqj_autotune(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
+                        const char *cache_path, dqj_schedule *best);
+
+/* dqj_render with an explicit schedule (NULL = autotuned or default). */
 dqj_status dqj_render_scheduled(const dqj_params *params, const dqj_frame_out *out,
                                 const dqj_schedule *sched, void *hip_stream);
 

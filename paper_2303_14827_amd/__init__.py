@@ -161,6 +161,8 @@ _SIGS = {
     "dqj_classify_points": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(dqj_params),
                                         C.c_void_p, C.c_void_p, C.c_void_p]),
     "dqj_device_info_get": (C.c_int32, [C.c_int32, C.POINTER(dqj_device_info)]),
+    "dqj_autotune": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out), C.c_int32,
+                                 C.c_char_p, C.POINTER(dqj_schedule)]),
     "dqj_serve_create": (C.c_int32, [C.POINTER(dqj_serve_config), C.POINTER(C.c_void_p)]),
     "dqj_serve_submit": (C.c_int32, [C.c_void_p, C.POINTER(dqj_params), C.POINTER(dqj_frame_out),
                                      C.POINTER(C.c_uint64)]),
@@ -322,6 +324,17 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(ps: Sequence, outs: List[Dict], cache_path: Optional[str] = None) -> dqj_schedule:
+    """Pick the fastest schedule for frames like ps (renders them into outs)."""
+    n = len(ps)
+    arr_p = (dqj_params * n)(*[make_params(p) for p in ps])
+    arr_o = (dqj_frame_out * n)(*[make_frame_out(o) for o in outs])
+    best = make_schedule()
+    _check(lib().dqj_autotune(arr_p, arr_o, n, cache_path.encode() if cache_path else None,
+                              C.byref(best)))
+    return best
 
 
 def classify_points(pts, p, precision: int = PREC_FP32, stream=None):

@@ -130,7 +130,8 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
     int cus = 0;
     dqj_status st = current_device(nullptr, &cus);
     if (st != DQJ_OK) return st;
-    const Sched s = resolve_schedule(nullptr, cus);
+    if (n < 1 || !params) return fail(DQJ_E_INVALID, "batch size must be >= 1 with params");
+    const Sched s = pick_schedule(nullptr, params[0], cus);
     std::vector<FrameDesc> table;
     uint32_t total = 0;
     int norm = 0;
@@ -198,7 +199,8 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     if (sched && sched->struct_size != sizeof(dqj_schedule))
       return fail(DQJ_E_INVALID, "schedule.struct_size %u != %zu", sched->struct_size,
                   sizeof(dqj_schedule));
-    const Sched s = resolve_schedule(sched, cus);
+    if (n < 1 || !params) return fail(DQJ_E_INVALID, "batch size must be >= 1 with params");
+    const Sched s = pick_schedule(sched, params[0], cus);
     if (s.kernel == DQJ_KERNEL_DIRECT)
       return fail(DQJ_E_UNSUPPORTED, "batched renders use the refill kernel");
     std::vector<FrameDesc> table;

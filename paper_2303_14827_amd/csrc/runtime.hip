@@ -390,10 +390,10 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
   hipError_t e;
   switch (params->precision) {
     case DQJ_PREC_FP32:
-      e = launch_render_fp32(kp, ko, resolve_schedule(sched, cus), cus, stream);
+      e = launch_render_fp32(kp, ko, pick_schedule(sched, *params, cus), cus, stream);
       break;
     case DQJ_PREC_SPLIT: {
-      const Sched s = resolve_schedule(sched, cus);
+      const Sched s = pick_schedule(sched, *params, cus);
       FrameDesc f;
       memset(&f, 0, sizeof f);
       f.P = kp;

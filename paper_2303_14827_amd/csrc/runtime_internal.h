@@ -25,6 +25,16 @@ struct Sched {
 };
 Sched resolve_schedule(const dqj_schedule *s, int cus);
 
+// Schedule remembered by the autotuner for this workload (false if none).
+bool tuned_schedule(const dqj_params &p, Sched *out);
+
+// Explicit schedule if given, else the autotuned one for p, else the defaults.
+inline Sched pick_schedule(const dqj_schedule *s, const dqj_params &p, int cus) {
+  Sched t;
+  if (!s && tuned_schedule(p, &t)) return t;
+  return resolve_schedule(s, cus);
+}
+
 // FP32 render of one frame with a schedule (s may be null: defaults).
 hipError_t launch_render_fp32(const KParams &P, const KOut &out, const Sched &s, int cus,
                               hipStream_t stream);

@@ -270,3 +270,25 @@ def test_batch_matches_single_and_graph_replays(dqj):
             for k in ("mask", "depth", "shade", "iters"):
                 np.testing.assert_array_equal(o[k], s[k], err_msg=f"replay {rep} {k}")
     plan.close()
+
+
+def test_autotune_remembers_and_keeps_images(dqj, tmp_path):
+    import torch
+    ps = workloads.sweep_256(6, first_seed=200)
+    ref = [render_np(dqj, p) for p in ps]
+    outs = [dqj.alloc_outputs(p.width, p.height) for p in ps]
+    cache = tmp_path / "tune.jsonl"
+    best = dqj.autotune(ps, outs, str(cache))
+    say("autotuned", best.tile_w, best.tile_h, best.waves_per_block, best.blocks_per_cu)
+    line = cache.read_text().strip().splitlines()[-1]
+    assert "W=256,H=256,N=16,S=256,B=8" in line and f'"tile_w": {best.tile_w}' in line
+    # a plan without an explicit schedule now uses the tuned one; images are unchanged
+    outs2 = [dqj.alloc_outputs(p.width, p.height) for p in ps]
+    plan = dqj.BatchPlan(ps, outs2)
+    plan.launch()
+    torch.cuda.synchronize()
+    for o, r in zip(outs2, ref):
+        o = to_numpy(o)
+        for k in ("mask", "depth", "shade", "normal", "iters"):
+            np.testing.assert_array_equal(o[k], r[k], err_msg=k)
+    plan.close()
