@@ -274,6 +274,9 @@ def bench_sweep(args, dqj, workloads, torch):
     outs = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
     tune_n = min(64, n)
     best = dqj.autotune(ps[:tune_n], outs[:tune_n])
+    for o in outs[:tune_n]:
+        o["iters"].zero_()           # the tuning launches counted into these
+    torch.cuda.synchronize()
     sched = {"tile_w": best.tile_w, "tile_h": best.tile_h, "waves_per_block": best.waves_per_block,
              "blocks_per_cu": best.blocks_per_cu}
     cplan = dqj.BatchPlan(ps, outs)          # uses the autotuned schedule

@@ -226,6 +226,25 @@ __device__ __forceinline__ uint32_t finish_ray(const P_T &P, const T *c, int N, 
   return it;
 }
 
+// Add each lane's count v to the counter of its frame f (f < 0: nothing), with one
+// atomic per distinct frame in the wave. Every lane of the wave must call it.
+template <typename FPtrT>
+__device__ __forceinline__ void wave_add_by_frame(int f, unsigned long long v, FPtrT F) {
+  uint64_t pending = __builtin_amdgcn_ballot_w64(f >= 0 && v != 0);
+  const int lane = lane_id();
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const int lf = __shfl(f, leader, 64);
+    const bool mine = f == lf && f >= 0 && v != 0;
+    unsigned long long x = mine ? v : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    x = __shfl(x, 0, 64);
+    if (lane == leader && F->out.iters) atomicAdd(F->out.iters, x);
+    pending &= ~__builtin_amdgcn_ballot_w64(mine);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -453,50 +472,60 @@ __global__ __launch_bounds__(256) void refine_fp32_kernel(FrameDesc single,
                                                           SplitEntry *__restrict__ amb) {
   const ConstFrame ctable = (ConstFrame)table;
   const uint32_t n = ctr[1];
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-    const SplitEntry en = hits[e];
-    const FrameDesc *Fg = nullptr;
+  // wave-uniform loop: each wave takes 64 consecutive entries per step, so its lanes
+  // meet again at the end of every step for the work-counter reduction
+  const uint32_t wave0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = wave0; base < n; base += stride) {
+    const uint32_t e = base + (threadIdx.x & 63u);
+    uint32_t it = 0;
+    int fr = -1;
     typename FramePtr<BATCH>::type F;
     if constexpr (BATCH)
-      F = ctable + en.frame;
+      F = ctable;
     else
       F = &single;
-    (void)Fg;
-    const KParams &P = F->P;
-    const int i = (int)(en.pix % (uint32_t)P.W), j = (int)(en.pix / (uint32_t)P.W);
-    float d[3], t0, t1;
-    pixel_dir(P, i, j, d);
-    clip_box(P, d, t0, t1);
-    const float dt = (t1 - t0) / (float)P.S;
-    const int w = P.fp64_window;
-    const int kh = en.khat;
-    const int klo = kh - w > 0 ? kh - w : 0;
-    const int khi = kh + w < P.S ? kh + w : P.S;
-    uint32_t in_mask = 0, it = 0;
-    for (int k = klo; k <= khi; ++k) {
-      bool in;
-      float n2;
-      it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)k, dt, t0), d, 0.0f, 0.0f, 0.0f, &in, &n2);
-      in_mask |= (in ? 1u : 0u) << (k - klo);
+    if (e < n) {
+      const SplitEntry en = hits[e];
+      if constexpr (BATCH) F = ctable + en.frame;
+      fr = (int)en.frame;
+      const KParams &P = F->P;
+      const int i = (int)(en.pix % (uint32_t)P.W), j = (int)(en.pix / (uint32_t)P.W);
+      float d[3], t0, t1;
+      pixel_dir(P, i, j, d);
+      clip_box(P, d, t0, t1);
+      const float dt = (t1 - t0) / (float)P.S;
+      const int w = P.fp64_window;
+      const int kh = en.khat;
+      const int klo = kh - w > 0 ? kh - w : 0;
+      const int khi = kh + w < P.S ? kh + w : P.S;
+      uint32_t in_mask = 0;
+      for (int k = klo; k <= khi; ++k) {
+        bool in;
+        float n2;
+        it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)k, dt, t0), d, 0.0f, 0.0f, 0.0f, &in,
+                               &n2);
+        in_mask |= (in ? 1u : 0u) << (k - klo);
+      }
+      // The FP32 window decides the crossing when its classes are monotone
+      // (out ... out in ... in) with the change inside the window: an outside sample
+      // before the first inside one, or the first inside one is sample 0.
+      const uint32_t full = (2u << (khi - klo)) - 1u;
+      const uint32_t low = in_mask & (0u - in_mask);
+      const bool monotone = in_mask != 0 && ((in_mask | (low - 1u)) == full);
+      const int kfirst = klo + (in_mask ? __builtin_ctz(in_mask) : 0);
+      const bool decided = monotone && (kfirst > klo || kfirst == 0);
+      if (decided) {
+        PixelOut r;
+        it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, kfirst,
+                               (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+        write_pixel(F->out, en.pix, r);
+      } else {
+        const uint32_t slot = atomicAdd(amb_ctr, 1u);
+        amb[slot] = en;
+      }
     }
-    // The FP32 window decides the crossing when its classes are monotone
-    // (out ... out in ... in) with the change inside the window: an outside sample
-    // before the first inside one, or the first inside one is sample 0.
-    const uint32_t full = (2u << (khi - klo)) - 1u;
-    const uint32_t low = in_mask & (0u - in_mask);
-    const bool monotone = in_mask != 0 && ((in_mask | (low - 1u)) == full);
-    const int kfirst = klo + (in_mask ? __builtin_ctz(in_mask) : 0);
-    const bool decided = monotone && (kfirst > klo || kfirst == 0);
-    if (decided) {
-      PixelOut r;
-      it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, kfirst,
-                             (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
-      write_pixel(F->out, en.pix, r);
-    } else {
-      const uint32_t slot = atomicAdd(amb_ctr, 1u);
-      amb[slot] = en;
-    }
-    if (COUNT && F->out.iters) atomicAdd(F->out.iters, (unsigned long long)it);
+    if (COUNT) wave_add_by_frame(fr, it, F);
   }
 }
 
@@ -510,56 +539,64 @@ __global__ __launch_bounds__(256) void rebisect_fp64_kernel(FrameDesc single,
                                                             const SplitEntry *__restrict__ amb) {
   const ConstFrame ctable = (ConstFrame)table;
   const uint32_t n = *amb_ctr;
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-    const SplitEntry en = amb[e];
+  const uint32_t wave0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = wave0; base < n; base += stride) {
+    const uint32_t e = base + (threadIdx.x & 63u);
+    uint32_t it = 0;
+    int fr = -1;
     typename FramePtr<BATCH>::type F;
     if constexpr (BATCH)
-      F = ctable + en.frame;
+      F = ctable;
     else
       F = &single;
-    const KParams64 &Q = F->P64;
-    const int W = F->P.W, S = F->P.S, N = F->P.N, B = F->P.B;
-    const int i = (int)(en.pix % (uint32_t)W), j = (int)(en.pix / (uint32_t)W);
-    double d[3], t0, t1;
-    pixel_dir64(Q, i, j, d);
-    uint32_t it = 0;
-    PixelOut r;
-    if (!clip_box64(Q, d, t0, t1)) {
-      r = miss_pixel(DQJ_FLAG_FP64);
-    } else {
-      const double dt = (t1 - t0) / (double)S;
-      const int w = F->P.fp64_window;
-      int klo = en.khat - w > 0 ? en.khat - w : 0;
-      int kstar = -1;
-      for (int k = klo; k <= S; ++k) {
-        bool in;
-        double n2;
-        it += classify_t<NORM>(Q, Q.c, N, Q.R2, fma((double)k, dt, t0), d, 0.0, 0.0, 0.0, &in, &n2);
-        if (in) {
-          kstar = k;
-          break;
+    if (e < n) {
+      const SplitEntry en = amb[e];
+      if constexpr (BATCH) F = ctable + en.frame;
+      fr = (int)en.frame;
+      const KParams64 &Q = F->P64;
+      const int W = F->P.W, S = F->P.S, N = F->P.N, B = F->P.B;
+      const int i = (int)(en.pix % (uint32_t)W), j = (int)(en.pix / (uint32_t)W);
+      double d[3], t0, t1;
+      pixel_dir64(Q, i, j, d);
+      PixelOut r;
+      if (!clip_box64(Q, d, t0, t1)) {
+        r = miss_pixel(DQJ_FLAG_FP64);
+      } else {
+        const double dt = (t1 - t0) / (double)S;
+        const int w = F->P.fp64_window;
+        int klo = en.khat - w > 0 ? en.khat - w : 0;
+        int kstar = -1;
+        for (int k = klo; k <= S; ++k) {
+          bool in;
+          double n2;
+          it += classify_t<NORM>(Q, Q.c, N, Q.R2, fma((double)k, dt, t0), d, 0.0, 0.0, 0.0, &in, &n2);
+          if (in) {
+            kstar = k;
+            break;
+          }
+        }
+        // The window starts inside: the FP16 march crossed late. Walk back to the start
+        // of this inside run (samples before an outside one are not re-checked).
+        while (kstar == klo && kstar > 0) {
+          bool in;
+          double n2;
+          it += classify_t<NORM>(Q, Q.c, N, Q.R2, fma((double)(kstar - 1), dt, t0), d, 0.0, 0.0,
+                                 0.0, &in, &n2);
+          if (!in) break;
+          --kstar;
+          --klo;
+        }
+        if (kstar < 0) {
+          r = miss_pixel(DQJ_FLAG_BOX | DQJ_FLAG_FP64);
+        } else {
+          it += finish_ray<NORM>(Q, Q.c, N, B, Q.R2, Q.h, d, t0, dt, kstar,
+                                 (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT | DQJ_FLAG_FP64), r);
         }
       }
-      // The window starts inside: the FP16 march crossed late. Walk back to the start
-      // of this inside run (samples before an outside one are not re-checked).
-      while (kstar == klo && kstar > 0) {
-        bool in;
-        double n2;
-        it += classify_t<NORM>(Q, Q.c, N, Q.R2, fma((double)(kstar - 1), dt, t0), d, 0.0, 0.0, 0.0,
-                               &in, &n2);
-        if (!in) break;
-        --kstar;
-        --klo;
-      }
-      if (kstar < 0) {
-        r = miss_pixel(DQJ_FLAG_BOX | DQJ_FLAG_FP64);
-      } else {
-        it += finish_ray<NORM>(Q, Q.c, N, B, Q.R2, Q.h, d, t0, dt, kstar,
-                               (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT | DQJ_FLAG_FP64), r);
-      }
+      write_pixel(F->out, en.pix, r);
     }
-    write_pixel(F->out, en.pix, r);
-    if (COUNT && F->out.iters) atomicAdd(F->out.iters, (unsigned long long)it);
+    if (COUNT) wave_add_by_frame(fr, it, F);
   }
 }
 
