@@ -331,6 +331,9 @@ def main():
     ap.add_argument("--error-pixels", type=int, default=4000)
     ap.add_argument("--sweep-frames", type=int, default=4096)
     ap.add_argument("--sweep-oracle-frames", type=int, default=16)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (a known-size kernel that "
+                         "calibrates hardware byte counters under a profiler)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -342,6 +345,13 @@ def main():
     import torch
     import paper_2303_14827_amd as dqj
     import workloads
+
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if args.workload != "plain_1024":
         torch.cuda.set_device(0)

@@ -108,6 +108,10 @@ def test_refusals_cancel_timeout(dqj):
         # a slow request holds the only in-flight slot; the next ones queue
         slow = base.replace(width=300, height=300, max_iter=64, march_steps=1024)
         t1 = srv.submit(slow, dqj.alloc_outputs(300, 300, extras=False))
+        deadline = time.monotonic() + 10.0
+        while srv.poll(t1)["t_admit"] < 0:           # the scheduler thread admits it
+            assert time.monotonic() < deadline
+            time.sleep(0.0002)
         t2 = srv.submit(base, dqj.alloc_outputs(128, 128, extras=False))
         t3 = srv.submit(base, dqj.alloc_outputs(128, 128, extras=False))
         st, _ = srv.submit_status(base, dqj.alloc_outputs(128, 128, extras=False))
