@@ -25,13 +25,14 @@ namespace {
 // Host-side validation and packing shared by the eager and the captured batch.
 dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
                       const Sched &s, std::vector<FrameDesc> &table, uint32_t &total_tiles,
-                      int &norm, bool &all_axis, bool &any_count, int &precision,
-                      uint64_t &pixels) {
+                      int &norm, bool &all_axis, int &slice_mode, bool &any_count,
+                      int &precision, uint64_t &pixels) {
   if (n < 1) return fail(DQJ_E_INVALID, "batch size must be >= 1 (got %d)", n);
   if (!params || !outs) return fail(DQJ_E_INVALID, "params and outs are required");
   table.resize(n);
   uint64_t tiles = 0;
   all_axis = true;
+  slice_mode = kSliceIdentitySticky;
   any_count = false;
   pixels = 0;
   for (int32_t i = 0; i < n; ++i) {
@@ -55,6 +56,7 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
     set_tiles(f, s.tile_w, s.tile_h);
     tiles += f.ntiles;
     all_axis = all_axis && f.P.axis_slice;
+    slice_mode = combine_slice_mode(slice_mode, slice_mode_of(f.P));
     any_count = any_count || f.out.iters != nullptr;
   }
   if (tiles >= (1ull << 31)) return fail(DQJ_E_INVALID, "batch has too many tiles (%llu)",
@@ -136,9 +138,11 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
     uint32_t total = 0;
     int norm = 0;
     bool all_axis = true, any_count = false;
+    int slice_mode = kSliceGeneral;
     int precision = 0;
     uint64_t pixels = 0;
-    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count, precision, pixels);
+    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, slice_mode, any_count, precision,
+                    pixels);
     if (st != DQJ_OK) return st;
     reap_retired(false);
     hipStream_t stream = (hipStream_t)hip_stream;
@@ -157,7 +161,7 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
       uint32_t *counter = nullptr;
       if (e == hipSuccess) e = stream_counter(stream, &counter);
       if (e == hipSuccess)
-        e = launch_render_refill_batch((const FrameDesc *)r.dev, nullptr, n, total, norm, all_axis,
+        e = launch_render_refill_batch((const FrameDesc *)r.dev, nullptr, n, total, norm, slice_mode,
                                        any_count, counter, s, cus, stream);
     } else {
       void *scratch = nullptr;
@@ -207,9 +211,11 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     uint32_t total = 0;
     int norm = 0;
     bool all_axis = true, any_count = false;
+    int slice_mode = kSliceGeneral;
     int precision = 0;
     uint64_t pixels = 0;
-    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, any_count, precision, pixels);
+    st = pack_batch(params, outs, n, s, table, total, norm, all_axis, slice_mode, any_count, precision,
+                    pixels);
     if (st != DQJ_OK) return st;
     p = new dqj_batch_plan;
     p->dev = dev;
@@ -230,7 +236,7 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
       // The capture holds a counter-reset kernel (not a memset node) and the kernel.
       hipError_t le =
           precision == DQJ_PREC_FP32
-              ? launch_render_refill_batch(p->table_dev, nullptr, n, total, norm, all_axis, any_count,
+              ? launch_render_refill_batch(p->table_dev, nullptr, n, total, norm, slice_mode, any_count,
                                            p->counter_dev, s, cus, p->cap_stream)
               : launch_render_split_batch(p->table_dev, nullptr, n, total, norm, all_axis, any_count,
                                           split_scratch_at(p->split_scratch, pixels), s, cus,

@@ -33,7 +33,9 @@ struct alignas(16) KParams {
   int32_t norm;          // 0: 8 squares, 1: real part only
   int32_t axis_slice;    // 1 if O = 0 and U, V, W = e0, e1, e2 (zeta_0 = (X, Y, Z, 0 | 0))
   int32_t fp64_window;   // split precision verify window
-  int32_t pad[2];
+  int32_t sticky1;       // 1 if, on the identity slice, escaping on the first update
+                         // implies escaping on the second (see pack_params)
+  int32_t pad;
 };
 static_assert(sizeof(KParams) % 16 == 0, "KParams must be 16-byte sized");
 

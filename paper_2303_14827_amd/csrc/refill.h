@@ -11,11 +11,19 @@ namespace dqj {
 hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
                                 hipStream_t stream);
 
-// n frames from a device-resident table; all frames share norm; all_axis is true only
-// if every frame uses the identity slice.
+// Slice modes of a launch, ordered so that the mode of several frames is the minimum
+// of theirs: general slice; identity slice (first march update in closed form);
+// identity slice whose escape guarantees let the first update go untested.
+enum { kSliceGeneral = 0, kSliceIdentity = 1, kSliceIdentitySticky = 2 };
+int slice_mode_of(const KParams &P);
+int combine_slice_mode(int a, int b);
+
+// n frames from a device-resident table; all frames share norm; slice_mode is the
+// combined mode of all frames (for a launch whose table changes between graph replays,
+// the least mode any table may have).
 // hdr_dev (may be null) overrides nframes/total_tiles with values read on the device.
 hipError_t launch_render_refill_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
-                                      int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                      int nframes, uint32_t total_tiles, int norm, int slice_mode,
                                       bool any_count, uint32_t *counter, const Sched &s, int cus,
                                       hipStream_t stream);
 

@@ -95,13 +95,19 @@ __device__ __forceinline__ void start_point(const KParams &P, float x, float y, 
 
 }  // namespace
 
-template <int NORM, bool AXIS, bool BATCH, bool COUNT>
+// Template switches: NORM (escape norm), AXIS (every frame uses the identity slice,
+// so march samples take their first update in closed form), BATCH (frames come from a
+// device table), COUNT (accumulate executed updates per frame), STICKY (every frame
+// guarantees that a march sample escaping on its first update escapes on the second,
+// so that update is not tested; only used with AXIS and without COUNT).
+template <int NORM, bool AXIS, bool BATCH, bool COUNT, bool STICKY>
 __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
                                                              const FrameDesc *__restrict__ table,
                                                              const LaunchHeader *__restrict__ hdr,
                                                              int nframes, uint32_t total_tiles,
                                                              uint32_t *__restrict__ counter,
                                                              int TW, int TH) {
+  static_assert(!STICKY || (AXIS && !COUNT), "STICKY needs AXIS and no counting");
   const int lane = lane_id();
   const int tile_rays = TW * TH;
   if constexpr (BATCH) {
@@ -131,18 +137,22 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
   float R2 = 0.0f, c3sq = 0.0f, cdsq = 0.0f, Sf = 0.0f;
   float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // eye (cached: the table is not provably read-only)
   int N = 1;
-  bool closed_first = false;   // first march update in closed form (identity slice, N > 1)
+  bool n_is_1 = false;
   // Trip counter: one update per trip. A point started in trip t has had trip - t
-  // updates after trip `trip`, so "max_iter reached" is trip >= deadline, with the
-  // deadline set when the point starts; no per-lane counter is incremented.
+  // updates after trip `trip`, so "max_iter reached" is trip - deadline >= 0 (mod 2^32),
+  // with the deadline set when the point starts; no per-lane counter is incremented.
+  // A ray takes at most (S + B + 8) N <= 2^30 trips, so live deadlines lie less than
+  // 2^30 ahead and an idle lane's deadline (2^31 - 1 ahead) is never reached before
+  // the lane gets a new ray or the wave ends.
   uint32_t trip = 0;
+  const uint32_t kIdleAhead = 0x7FFFFFFFu;
 
   // ---- per-lane state. Idle lanes sit on a NaN state (never escapes) with a far
   // deadline, so they never retire and need no separate test.
   int phase = PH_IDLE;
   DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
   float s = kNaN;
-  uint32_t dl = 1u << 30;
+  uint32_t dl = kIdleAhead;
   int pix = 0;
   float dx = 0, dy = 0, dz = 0, t0 = 0, dt = 0;
   float k = kNoMarch;     // march sample index (exact in FP32 up to 2^24)
@@ -155,143 +165,152 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
     // ---- one update on every lane
     const float n2 = dq_update_hot<NORM>(z, s, c);
     const bool esc = n2 > R2;
-    const bool done = esc || (int)(trip - dl) >= 0;
+    // Fast path: an outside march sample with more samples to go starts the next one.
+    // Everything else that retires (a march hit or miss, a bisection or normal point)
+    // takes the slow path, which runs first: it never leaves a lane that would pass
+    // the fast test (it sets k past the march or idles the lane), so the fast test
+    // after it picks exactly the lanes it would have picked before.
+    const bool slow = !(esc && k < Sf) && (esc || (int)(trip - dl) >= 0);
 
-    if (done) {
-      // Fast path: an outside march sample with more samples to go starts the next
-      // sample here. With the identity slice its first update is taken in closed form
-      // (zeta_0 = (x, y, z, 0 | 0) gives z_1 = (x^2 - y^2 - z^2 + c0, 2xy + c1, 2xz + c2,
-      // c3 | c_d)); a sample that escapes on that update is parked on a state that
-      // escapes on the next one, so it retires with escape index 1.
-      const bool fast = esc && k < Sf;
-      if (fast) {
-        if (COUNT) it_lane += (uint32_t)N - (dl - trip);
-        k += 1.0f;
-        const float t = fmaf(k, dt, t0);
-        const float x = fmaf(t, dx, ex);
-        const float y = fmaf(t, dy, ey);
-        const float w = fmaf(t, dz, ez);
-        if (AXIS && closed_first) {
-          const float s0 = fmaf(w, w, y * y);
-          const float tx = x + x;
-          const float a0 = fmaf(x, x, c[0] - s0);
-          z.a1 = fmaf(tx, y, c[1]);
-          z.a2 = fmaf(tx, w, c[2]);
-          z.a3 = c[3];
-          z.b0 = c[4];
-          z.b1 = c[5];
-          z.b2 = c[6];
-          z.b3 = c[7];
-          s = fmaf(z.a2, z.a2, fmaf(z.a1, z.a1, c3sq));
-          const bool esc1 = fmaf(a0, a0, s + cdsq) > R2;
-          z.a0 = esc1 ? 1e18f : a0;
-          dl = trip + (uint32_t)N - (esc1 ? 0u : 1u);
-        } else {
-          start_point<AXIS>(F->P, x, y, w, z, s);
-          dl = trip + (uint32_t)N;
-        }
-      }
-      // Everything else (a march hit or miss, a bisection or normal point) is rare: a
-      // separate wave-uniform test keeps its code off the fast path (an if/else here
-      // makes the compiler copy the lane state at the join on every trip).
-      if (done && !fast) {
-        const KParams &P = F->P;
-        const bool inside = !esc;
-        const int m = N - (int)(dl - trip);   // escape index, or N when inside
-        if (COUNT) it_lane += (uint32_t)m;
-        bool next_normal = false;
-        bool restart = false;   // start the point at parameter tr on the ray
-        float tr = 0.0f;
-        if (phase == PH_MARCH) {
-          if (inside) {
-            kstar = (int)k;
-            k = kNoMarch;
-            if (kstar == 0) {
-              thit = t0;
-              next_normal = true;
-            } else {
-              lo = fmaf((float)(kstar - 1), dt, t0);
-              hi = fmaf((float)kstar, dt, t0);
-              if (P.B == 0) {
-                thit = 0.5f * (lo + hi);
-                next_normal = true;
-              } else {
-                b = 0;
-                phase = PH_BISECT;
-                tr = 0.5f * (lo + hi);
-                restart = true;
-              }
-            }
-          } else {  // the last sample was outside: the ray misses
-            write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
-            phase = PH_IDLE;
-          }
-        } else if (phase == PH_BISECT) {
-          const float tm = 0.5f * (lo + hi);
-          if (inside)
-            hi = tm;
-          else
-            lo = tm;
-          ++b;
-          if (b >= P.B) {
-            thit = 0.5f * (lo + hi);
+    if (slow) {
+      const KParams &P = F->P;
+      // (recomputed from an opaque copy: a shared compare would run on every trip)
+      float n2c = n2;
+      asm volatile("" : "+v"(n2c));
+      const bool inside = !(n2c > R2);
+      const int m = N - (int)(dl - trip);   // escape index, or N when inside
+      if (COUNT) it_lane += (uint32_t)m;
+      bool next_normal = false;
+      bool restart = false;   // start the point at parameter tr on the ray
+      float tr = 0.0f;
+      if (phase == PH_MARCH) {
+        if (inside) {
+          kstar = (int)k;
+          k = kNoMarch;
+          if (kstar == 0) {
+            thit = t0;
             next_normal = true;
           } else {
-            tr = 0.5f * (lo + hi);
-            restart = true;
+            lo = fmaf((float)(kstar - 1), dt, t0);
+            hi = fmaf((float)kstar, dt, t0);
+            if (P.B == 0) {
+              thit = 0.5f * (lo + hi);
+              next_normal = true;
+            } else {
+              b = 0;
+              phase = PH_BISECT;
+              tr = 0.5f * (lo + hi);
+              restart = true;
+            }
           }
-        } else {  // PH_NORMAL: stencil point sidx just retired
-          const float G = potential(n2, m);
-          const float sg = (sidx & 1) ? -G : G;
-          const int axis = sidx >> 1;
-          if (axis == 0)
-            gx += sg;
-          else if (axis == 1)
-            gy += sg;
-          else
-            gz += sg;
-          ++sidx;
-          if (sidx == 6) {
-            const float g[3] = {gx, gy, gz};
-            const float d[3] = {dx, dy, dz};
-            PixelOut r;
-            finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
-            write_pixel(F->out, pix, r);
-            phase = PH_IDLE;
-          }
+        } else {  // the last sample was outside: the ray misses
+          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+          phase = PH_IDLE;
         }
-        if (next_normal) {
-          phase = PH_NORMAL;
-          sidx = 0;
-          gx = gy = gz = 0.0f;
-        }
-        float px = 0, py = 0, pz = 0;
-        if (restart) {
-          px = fmaf(tr, dx, ex);
-          py = fmaf(tr, dy, ey);
-          pz = fmaf(tr, dz, ez);
-        } else if (phase == PH_NORMAL) {
-          const int axis = sidx >> 1;
-          const float hs = (sidx & 1) ? -P.h : P.h;
-          px = fmaf(thit, dx, ex) + (axis == 0 ? hs : 0.0f);
-          py = fmaf(thit, dy, ey) + (axis == 1 ? hs : 0.0f);
-          pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
-        }
-        if (phase != PH_IDLE) {
-          start_point<AXIS>(P, px, py, pz, z, s);
-          dl = trip + (uint32_t)N;
+      } else if (phase == PH_BISECT) {
+        const float tm = 0.5f * (lo + hi);
+        if (inside)
+          hi = tm;
+        else
+          lo = tm;
+        ++b;
+        if (b >= P.B) {
+          thit = 0.5f * (lo + hi);
+          next_normal = true;
         } else {
-          z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
-          s = kNaN;
-          dl = trip + (1u << 30);
+          tr = 0.5f * (lo + hi);
+          restart = true;
         }
+      } else {  // PH_NORMAL: stencil point sidx just retired
+        const float G = potential(n2, m);
+        const float sg = (sidx & 1) ? -G : G;
+        const int axis = sidx >> 1;
+        if (axis == 0)
+          gx += sg;
+        else if (axis == 1)
+          gy += sg;
+        else
+          gz += sg;
+        ++sidx;
+        if (sidx == 6) {
+          const float g[3] = {gx, gy, gz};
+          const float d[3] = {dx, dy, dz};
+          PixelOut r;
+          finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+          write_pixel(F->out, pix, r);
+          phase = PH_IDLE;
+        }
+      }
+      if (next_normal) {
+        phase = PH_NORMAL;
+        sidx = 0;
+        gx = gy = gz = 0.0f;
+      }
+      float px = 0, py = 0, pz = 0;
+      if (restart) {
+        px = fmaf(tr, dx, ex);
+        py = fmaf(tr, dy, ey);
+        pz = fmaf(tr, dz, ez);
+      } else if (phase == PH_NORMAL) {
+        const int axis = sidx >> 1;
+        const float hs = (sidx & 1) ? -P.h : P.h;
+        px = fmaf(thit, dx, ex) + (axis == 0 ? hs : 0.0f);
+        py = fmaf(thit, dy, ey) + (axis == 1 ? hs : 0.0f);
+        pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
+      }
+      if (phase != PH_IDLE) {
+        start_point<AXIS>(P, px, py, pz, z, s);
+        dl = trip + (uint32_t)N;
+      } else {
+        z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+        s = kNaN;
+        dl = trip + kIdleAhead;
       }
     }
 
-    // ---- hand new rays to idle lanes
-    for (;;) {
-      const uint64_t idle = __builtin_amdgcn_ballot_w64(phase == PH_IDLE);
-      if (!idle) break;
+    if (esc && k < Sf) {
+      if (COUNT) it_lane += (uint32_t)N - (dl - trip);
+      k += 1.0f;
+      const float t = fmaf(k, dt, t0);
+      const float x = fmaf(t, dx, ex);
+      const float y = fmaf(t, dy, ey);
+      const float w = fmaf(t, dz, ez);
+      if constexpr (AXIS) {
+        // First update in closed form: zeta_0 = (x, y, w, 0 | 0) gives
+        // zeta_1 = (x^2 - y^2 - w^2 + c0, 2xy + c1, 2xw + c2, c3 | c_d).
+        const float tx = x + x;
+        float a0 = fmaf(-w, w, fmaf(-y, y, fmaf(x, x, c[0])));
+        z.a1 = fmaf(tx, y, c[1]);
+        z.a2 = fmaf(tx, w, c[2]);
+        z.a3 = c[3];
+        z.b0 = c[4];
+        z.b1 = c[5];
+        z.b2 = c[6];
+        z.b3 = c[7];
+        s = fmaf(z.a2, z.a2, fmaf(z.a1, z.a1, c3sq));
+        if constexpr (STICKY) {
+          // zeta_2 escapes whenever zeta_1 does: leave zeta_1 untested (a sample that
+          // escaped on it retires after the next update, as a parked one would).
+          dl = trip + (uint32_t)(N - 1);
+        } else {
+          // Test zeta_1. An escaped sample is parked on a state that escapes on the
+          // next update (escape index 1); with max_iter 1 an inside one is parked on
+          // NaN (never escapes) and retires on its deadline at the next trip.
+          const bool esc1 = fmaf(a0, a0, s + cdsq) > R2;
+          a0 = esc1 ? 1e18f : (n_is_1 ? kNaN : a0);
+          dl = trip + (uint32_t)(N - 1) + ((esc1 || n_is_1) ? 1u : 0u);
+        }
+        z.a0 = a0;
+      } else {
+        start_point<AXIS>(F->P, x, y, w, z, s);
+        dl = trip + (uint32_t)N;
+      }
+    }
+
+    // ---- hand new rays to idle lanes (one exit: every stop leaves through the
+    // loop condition, so the common case costs one ballot and one branch)
+    uint64_t idle = __builtin_amdgcn_ballot_w64(phase == PH_IDLE);
+    while (idle) {
       if (!have_tile) {
         if (exhausted) break;
         if (!pending) {
@@ -316,6 +335,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           for (int q = 0; q < 8; ++q) c[q] = uniform_f(F->P.c[q]);
           R2 = uniform_f(F->P.R2);
           N = (int)uniform((uint32_t)F->P.N);
+          n_is_1 = N == 1;
           ex = uniform_f(F->P.eye[0]);
           ey = uniform_f(F->P.eye[1]);
           ez = uniform_f(F->P.eye[2]);
@@ -323,7 +343,6 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           c3sq = uniform_f(c[3] * c[3]);
           cdsq = NORM == 0 ? uniform_f(fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))))
                            : 0.0f;
-          closed_first = AXIS && N > 1;
         }
         tile_local = pend_tile - F->tile_begin + F->tile_offset;
         pending = false;
@@ -365,6 +384,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
       const int cnt = __popcll(idle);
       next_r += cnt < avail ? cnt : avail;
       if (next_r >= tile_rays) have_tile = false;
+      idle = __builtin_amdgcn_ballot_w64(phase == PH_IDLE);
     }
 
     if (exhausted && !__builtin_amdgcn_ballot_w64(phase != PH_IDLE)) break;
@@ -377,21 +397,28 @@ __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 template <bool BATCH, bool COUNT>
 static void launch_refill_variant(const FrameDesc &single, const FrameDesc *table,
                                   const LaunchHeader *hdr, int nframes,
-                                  uint32_t total_tiles, int norm, bool axis, uint32_t *counter,
+                                  uint32_t total_tiles, int norm, int mode, uint32_t *counter,
                                   const Sched &s, int blocks, int threads, hipStream_t stream) {
-#define DQJ_LAUNCH(NM, AX)                                                                    \
-  hipLaunchKernelGGL((render_refill_kernel<NM, AX, BATCH, COUNT>), dim3(blocks), dim3(threads), \
-                     0, stream, single, table, hdr, nframes, total_tiles, counter, s.tile_w, s.tile_h)
+#define DQJ_LAUNCH(NM, AX, ST)                                                                   \
+  hipLaunchKernelGGL((render_refill_kernel<NM, AX, BATCH, COUNT, ST>), dim3(blocks),             \
+                     dim3(threads), 0, stream, single, table, hdr, nframes, total_tiles, counter, \
+                     s.tile_w, s.tile_h)
+  // counting launches test every first update, so they never take the STICKY variant
+  if (COUNT && mode == kSliceIdentitySticky) mode = kSliceIdentity;
   if (norm == 0) {
-    if (axis)
-      DQJ_LAUNCH(0, true);
+    if (mode == kSliceGeneral)
+      DQJ_LAUNCH(0, false, false);
+    else if (COUNT || mode == kSliceIdentity)
+      DQJ_LAUNCH(0, true, false);
     else
-      DQJ_LAUNCH(0, false);
+      DQJ_LAUNCH(0, true, !COUNT);
   } else {
-    if (axis)
-      DQJ_LAUNCH(1, true);
+    if (mode == kSliceGeneral)
+      DQJ_LAUNCH(1, false, false);
+    else if (COUNT || mode == kSliceIdentity)
+      DQJ_LAUNCH(1, true, false);
     else
-      DQJ_LAUNCH(1, false);
+      DQJ_LAUNCH(1, true, !COUNT);
   }
 #undef DQJ_LAUNCH
 }
@@ -399,35 +426,42 @@ static void launch_refill_variant(const FrameDesc &single, const FrameDesc *tabl
 template <bool BATCH>
 static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *table,
                                      const LaunchHeader *hdr, int nframes,
-                                     uint32_t total_tiles, int norm, bool axis, bool count,
+                                     uint32_t total_tiles, int norm, int mode, bool count,
                                      uint32_t *counter, const Sched &s, int cus,
                                      hipStream_t stream) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
   const int threads = 64 * s.waves_per_block;
   const int blocks = cus * s.blocks_per_cu;
   if (count)
-    launch_refill_variant<BATCH, true>(single, table, hdr, nframes, total_tiles, norm, axis, counter,
+    launch_refill_variant<BATCH, true>(single, table, hdr, nframes, total_tiles, norm, mode, counter,
                                        s, blocks, threads, stream);
   else
-    launch_refill_variant<BATCH, false>(single, table, hdr, nframes, total_tiles, norm, axis, counter,
+    launch_refill_variant<BATCH, false>(single, table, hdr, nframes, total_tiles, norm, mode, counter,
                                         s, blocks, threads, stream);
   return hipGetLastError();
 }
 
+int slice_mode_of(const KParams &P) {
+  if (!P.axis_slice) return kSliceGeneral;
+  return P.sticky1 ? kSliceIdentitySticky : kSliceIdentity;
+}
+
+int combine_slice_mode(int a, int b) { return a < b ? a : b; }
+
 hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
                                 hipStream_t stream) {
   return launch_refill_impl<false>(frame, nullptr, nullptr, 1, frame.ntiles, frame.P.norm,
-                                   frame.P.axis_slice != 0, frame.out.iters != nullptr, counter, s,
+                                   slice_mode_of(frame.P), frame.out.iters != nullptr, counter, s,
                                    cus, stream);
 }
 
 hipError_t launch_render_refill_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
-                                      int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                      int nframes, uint32_t total_tiles, int norm, int slice_mode,
                                       bool any_count, uint32_t *counter, const Sched &s, int cus,
                                       hipStream_t stream) {
   FrameDesc dummy;
   memset(&dummy, 0, sizeof dummy);
-  return launch_refill_impl<true>(dummy, table_dev, hdr_dev, nframes, total_tiles, norm, all_axis,
+  return launch_refill_impl<true>(dummy, table_dev, hdr_dev, nframes, total_tiles, norm, slice_mode,
                                   any_count, counter, s, cus, stream);
 }
 

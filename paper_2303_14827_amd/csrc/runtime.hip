@@ -208,6 +208,23 @@ void pack_params(const dqj_params &p, KParams &k) {
   k.B = p.bisect_steps;
   k.norm = p.norm;
   k.fp64_window = p.fp64_window;
+  // On the identity slice zeta_0 = (x, y, z, 0 | 0), so zeta_1 = (a | c_d) with a real
+  // quaternion a. If zeta_1 escapes, |a|^2 > R^2 - |c_d|^2 (8 squares) or > R^2 (real
+  // part). The real part of zeta_2 is a^2 + c_r and the quaternion norm is
+  // multiplicative, so |a^2 + c_r| >= |a|^2 - |c_r|: once that bound on |a|^2 is at
+  // least R + |c_r|, zeta_2 escapes too. A 1% margin covers FP32 rounding of the
+  // state. Kernels then may let such a point run one more update instead of testing
+  // zeta_1 (the classification is the same; only the escape index differs).
+  {
+    double cr = 0, cd = 0;
+    for (int i = 0; i < 4; ++i) {
+      cr += (double)k.c[i] * (double)k.c[i];
+      cd += (double)k.c[4 + i] * (double)k.c[4 + i];
+    }
+    const double R = std::sqrt((double)k.R2);
+    const double q = (double)k.R2 - (p.norm == DQJ_NORM_REALPART ? 0.0 : cd);
+    k.sticky1 = (k.axis_slice && k.N > 1 && q >= 1.01 * (R + std::sqrt(cr)) + 1e-6) ? 1 : 0;
+  }
 }
 
 void pack_params64(const dqj_params &p, KParams64 &k) {

@@ -39,8 +39,9 @@ struct Slot {
   void *dev = nullptr;            // [LaunchHeader | FrameDesc x max_chunks]
   void *scratch = nullptr;        // split lists or the tile counter
   void *staging = nullptr;        // pinned copy of [header | table]
-  hipGraph_t graph[2] = {nullptr, nullptr};          // [general slice, identity slice]
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // one graph per slice mode: general, identity, identity with untested first update
+  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   bool busy = false;
   uint64_t epoch = 0;
 };
@@ -94,7 +95,7 @@ size_t slot_dev_bytes(int max_chunks) {
 void free_slots(dqj_server *s) {
   for (Slot &sl : s->slots) {
     if (sl.busy && sl.done) (void)hipEventSynchronize(sl.done);
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < 3; ++a) {
       if (sl.exec[a]) (void)hipGraphExecDestroy(sl.exec[a]);
       if (sl.graph[a]) (void)hipGraphDestroy(sl.graph[a]);
     }
@@ -107,21 +108,23 @@ void free_slots(dqj_server *s) {
   s->slots.clear();
 }
 
-// Capture the slot's two graphs (general and identity slice): a counter/list reset and
-// the persistent kernels, which take the epoch's size from the header in device memory.
+// Capture the slot's graphs (one per slice mode): a counter/list reset and the
+// persistent kernels, which take the epoch's size from the header in device memory.
+// (The split-precision march has no untested-first-update form: its last two graphs
+// are the same.)
 hipError_t capture_slot(dqj_server *s, Slot &sl) {
   const LaunchHeader *hdr = (const LaunchHeader *)sl.dev;
   const FrameDesc *table = (const FrameDesc *)((char *)sl.dev + sizeof(LaunchHeader));
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < 3; ++a) {
     hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le;
     if (s->precision == DQJ_PREC_SPLIT)
-      le = launch_render_split_batch(table, hdr, 0, 0, s->norm, a == 1, s->count,
+      le = launch_render_split_batch(table, hdr, 0, 0, s->norm, a >= 1, s->count,
                                      split_scratch_at(sl.scratch, s->epoch_pixels), s->sched,
                                      s->cus, sl.stream);
     else
-      le = launch_render_refill_batch(table, hdr, 0, 0, s->norm, a == 1, s->count,
+      le = launch_render_refill_batch(table, hdr, 0, 0, s->norm, a, s->count,
                                       (uint32_t *)sl.scratch, s->sched, s->cus, sl.stream);
     e = hipStreamEndCapture(sl.stream, &sl.graph[a]);
     if (le != hipSuccess) return le;
@@ -138,7 +141,7 @@ hipError_t launch_epoch(dqj_server *s, Slot &sl, const serve::Epoch &ep) {
   FrameDesc *tab = (FrameDesc *)((char *)sl.staging + sizeof(LaunchHeader));
   memset(h, 0, sizeof *h);
   uint32_t tile = 0;
-  bool all_axis = true;
+  int mode = kSliceIdentitySticky;
   for (size_t i = 0; i < ep.chunks.size(); ++i) {
     const serve::Chunk &c = ep.chunks[i];
     FrameDesc f = s->recs.at(c.ticket).frame;
@@ -147,13 +150,13 @@ hipError_t launch_epoch(dqj_server *s, Slot &sl, const serve::Epoch &ep) {
     f.ntiles = c.ntiles;
     tab[i] = f;
     tile += c.ntiles;
-    all_axis = all_axis && f.P.axis_slice;
+    mode = combine_slice_mode(mode, slice_mode_of(f.P));
   }
   h->nframes = (uint32_t)ep.chunks.size();
   h->total_tiles = tile;
   const size_t bytes = sizeof(LaunchHeader) + sizeof(FrameDesc) * ep.chunks.size();
   hipError_t e = hipMemcpyAsync(sl.dev, sl.staging, bytes, hipMemcpyHostToDevice, sl.stream);
-  if (e == hipSuccess) e = hipGraphLaunch(sl.exec[all_axis ? 1 : 0], sl.stream);
+  if (e == hipSuccess) e = hipGraphLaunch(sl.exec[mode], sl.stream);
   if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
   if (e == hipSuccess) {
     sl.busy = true;

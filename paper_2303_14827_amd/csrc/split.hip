@@ -36,9 +36,35 @@ struct DQH {
 };
 
 __device__ __forceinline__ h2 hfma(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }
+// Packed maximum that ignores a NaN operand. Written out because the generic form
+// first canonicalises its loop-carried operand (an extra instruction per update).
+__device__ __forceinline__ h2 hmax_raw(h2 a, h2 b) {
+  h2 r;
+  asm("v_pk_max_f16 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 __device__ __forceinline__ h2 hsplat(float v) { return h2{(_Float16)v, (_Float16)v}; }
 // Two FP32 values rounded to nearest FP16 and packed.
 __device__ __forceinline__ h2 hpack(float lo, float hi) { return h2{(_Float16)lo, (_Float16)hi}; }
+
+// Sample positions of a pair: (k0 D + X, k1 D + X) for three coordinates, each an FP32
+// fused multiply-add rounded to FP16, written straight into the packed halves with the
+// mixed-precision FMA (two instructions per coordinate instead of two FMAs and a
+// conversion). The closing s_nop gives the half-register writes the wait states a
+// dependent read needs.
+__device__ __forceinline__ void pair_points(float k0, float k1, float DX, float DY, float DZ,
+                                            float X0, float Y0, float Z0, h2 &x, h2 &y, h2 &w) {
+  asm("v_fma_mixlo_f16 %[x], %[k0], %[dx], %[x0]\n\t"
+      "v_fma_mixlo_f16 %[y], %[k0], %[dy], %[y0]\n\t"
+      "v_fma_mixlo_f16 %[w], %[k0], %[dz], %[z0]\n\t"
+      "v_fma_mixhi_f16 %[x], %[k1], %[dx], %[x0]\n\t"
+      "v_fma_mixhi_f16 %[y], %[k1], %[dy], %[y0]\n\t"
+      "v_fma_mixhi_f16 %[w], %[k1], %[dz], %[z0]\n\t"
+      "s_nop 1"
+      : [x] "=&v"(x), [y] "=&v"(y), [w] "=&v"(w)
+      : [k0] "v"(k0), [k1] "v"(k1), [dx] "v"(DX), [dy] "v"(DY), [dz] "v"(DZ), [x0] "v"(X0),
+        [y0] "v"(Y0), [z0] "v"(Z0));
+}
 
 // One packed update of two independent points (one per half), as dq_update.
 template <int NORM>
@@ -282,59 +308,53 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
   for (int q = 0; q < 8; ++q) c[q] = hsplat(0.0f);
   h2 c3sq = hsplat(0.0f), cdsq = hsplat(0.0f);
   _Float16 R2 = 0;
-  float Sf = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  float Sf = 0.0f, Sf2 = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
   int N = 1;
   bool closed_first = false;
+  // Trip counter, deadlines and their rebasing as in the FP32 marcher: idle lanes hold
+  // a NaN state (the running maximum ignores it) and the deadline 2^32 - 1.
   uint32_t trip = 0;
+  const uint32_t kIdleDl = 0xFFFFFFFFu;
+  const h2 kNaN2 = hsplat(__builtin_nanf(""));
 
   bool busy = false;
   DQH z;
-  z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = hsplat(0.0f);
-  h2 s = hsplat(0.0f), m2 = hsplat(0.0f);
-  uint32_t dl = 1u << 30;
+  z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = kNaN2;
+  h2 s = kNaN2, m2 = hsplat(0.0f);
+  uint32_t dl = kIdleDl;
   int pix = 0;
-  float dx = 0, dy = 0, dz = 0, t0 = 0, dt = 0, kp = 0.0f;   // kp: low sample of the pair
+  // Sample k of the ray is eye + (t0 + k dt) d, computed as k D + X0 with D = dt d and
+  // X0 = eye + t0 d (FP32, then rounded to FP16).
+  float X0 = 0, Y0 = 0, Z0 = 0, DX = 0, DY = 0, DZ = 0, kp = 0.0f;   // kp: low sample of the pair
   uint32_t cnt_lo = 0, cnt_hi = 0, it_lane = 0;
 
   for (;;) {
-    ++trip;
+    if (++trip >= 0x80000000u) {   // rebase (every live deadline is >= trip here)
+      asm volatile("" ::: "memory");   // a branch, not per-trip selects
+      trip -= 0x40000000u;
+      if (dl != kIdleDl) dl -= 0x40000000u;
+    }
     if (COUNT) {
       cnt_lo += (m2.x <= R2) ? 1u : 0u;
       cnt_hi += (m2.y <= R2) ? 1u : 0u;
     }
     const h2 n2 = pk_update<NORM>(z, s, c);
-    m2 = __builtin_elementwise_max(m2, n2);
-    const bool esc_lo = m2.x > R2, esc_hi = m2.y > R2;
-    const bool done = busy && ((esc_lo && esc_hi) || (int)(trip - dl) >= 0);
+    m2 = hmax_raw(m2, n2);
+    const bool both = m2.x > R2 && m2.y > R2;
+    const bool done = both || dl <= trip;
     if (done) {
-      bool start = false;
-      if (esc_lo && esc_hi && kp + 2.0f <= Sf) {   // both outside: next pair
+      // Fast path: both samples of the pair are outside and more samples follow.
+      const bool fast = both && kp <= Sf2;   // kp + 2 <= S (exact: small integers)
+      if (fast) {
         if (COUNT) it_lane += cnt_lo + cnt_hi;
         kp += 2.0f;
-        start = true;
-      } else {
-        if (esc_lo && esc_hi) {
-          if (COUNT) it_lane += cnt_lo + cnt_hi;
-          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
-        } else {
-          if (COUNT) it_lane += cnt_lo + (esc_lo ? cnt_hi : 0u);
-          const uint32_t slot = atomicAdd(ctr + 1, 1u);
-          hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, (int32_t)kp + (esc_lo ? 1 : 0), 0u};
-        }
-        busy = false;
-        m2 = hsplat(0.0f);
-        dl = trip + (1u << 30);
-      }
-      if (start) {
-        const float tl = fmaf(kp, dt, t0), th = fmaf(kp + 1.0f, dt, t0);
-        const h2 xh = hpack(fmaf(tl, dx, ex), fmaf(th, dx, ex));
-        const h2 yh = hpack(fmaf(tl, dy, ey), fmaf(th, dy, ey));
-        const h2 wh = hpack(fmaf(tl, dz, ez), fmaf(th, dz, ez));
+        const float k1 = kp + 1.0f;
         if (AXIS && closed_first) {
+          h2 xh, yh, wh;
+          pair_points(kp, k1, DX, DY, DZ, X0, Y0, Z0, xh, yh, wh);
           // z_1 of (x, y, w, 0 | 0) in closed form; m2 starts at ||z_1||^2
-          const h2 s0 = hfma(wh, wh, yh * yh);
           const h2 tx = xh + xh;
-          z.a0 = hfma(xh, xh, c[0] - s0);
+          z.a0 = hfma(-wh, wh, hfma(-yh, yh, hfma(xh, xh, c[0])));
           z.a1 = hfma(tx, yh, c[1]);
           z.a2 = hfma(tx, wh, c[2]);
           z.a3 = c[3];
@@ -348,9 +368,9 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           if (COUNT) cnt_lo = cnt_hi = 1;
         } else {
           const KParams &P = F->P;
-          const float xl = fmaf(tl, dx, ex), xhh = fmaf(th, dx, ex);
-          const float yl = fmaf(tl, dy, ey), yhh = fmaf(th, dy, ey);
-          const float wl = fmaf(tl, dz, ez), whh = fmaf(th, dz, ez);
+          const float xl = fmaf(kp, DX, X0), xhh = fmaf(k1, DX, X0);
+          const float yl = fmaf(kp, DY, Y0), yhh = fmaf(k1, DY, Y0);
+          const float wl = fmaf(kp, DZ, Z0), whh = fmaf(k1, DZ, Z0);
           const DQ<float> zl = slice_map<float>(P, xl, yl, wl);
           const DQ<float> zh = slice_map<float>(P, xhh, yhh, whh);
 #define DQJ_PK(F_) hpack(zl.F_, zh.F_)
@@ -368,10 +388,28 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           dl = trip + (uint32_t)N;
           if (COUNT) cnt_lo = cnt_hi = 0;
         }
-        if (kp + 1.0f > Sf) {   // the pair's high half is past the last sample
+        if (k1 > Sf) {   // the pair's high half is past the last sample (once per ray)
+          asm volatile("" ::: "memory");   // keep this a branch, not selects
           m2.y = (_Float16)INFINITY;
           if (COUNT) cnt_hi = 0;
         }
+      }
+      // The pair ends the march: a miss, or a hit at its first inside sample.
+      if (done && !fast) {
+        const bool esc_lo = m2.x > R2;
+        if (both) {
+          if (COUNT) it_lane += cnt_lo + cnt_hi;
+          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+        } else {
+          if (COUNT) it_lane += cnt_lo + (esc_lo ? cnt_hi : 0u);
+          const uint32_t slot = atomicAdd(ctr + 1, 1u);
+          hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, (int32_t)kp + (esc_lo ? 1 : 0), 0u};
+        }
+        busy = false;
+        z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = kNaN2;
+        s = kNaN2;
+        m2 = hsplat(0.0f);
+        dl = kIdleDl;
       }
     }
 
@@ -411,6 +449,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           ey = uniform_f(F->P.eye[1]);
           ez = uniform_f(F->P.eye[2]);
           Sf = uniform_f((float)F->P.S);
+          Sf2 = Sf - 2.0f;
           c3sq = hsplat(cf[3] * cf[3]);
           cdsq = hsplat(NORM == 0 ? cf[4] * cf[4] + cf[5] * cf[5] + cf[6] * cf[6] + cf[7] * cf[7] : 0.0f);
           closed_first = AXIS && N > 1;
@@ -433,11 +472,13 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           pixel_dir(P, i, j, d);
           float ta, tb;
           if (clip_box(P, d, ta, tb)) {
-            dx = d[0];
-            dy = d[1];
-            dz = d[2];
-            t0 = ta;
-            dt = (tb - ta) / (float)P.S;
+            const float dt = (tb - ta) / (float)P.S;
+            X0 = fmaf(ta, d[0], ex);
+            Y0 = fmaf(ta, d[1], ey);
+            Z0 = fmaf(ta, d[2], ez);
+            DX = dt * d[0];
+            DY = dt * d[1];
+            DZ = dt * d[2];
             // enter as if the pair (-2, -1) had just escaped: the next trip starts pair 0
             kp = -2.0f;
             busy = true;
