@@ -134,7 +134,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
   float c[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) c[q] = 0.0f;
-  float R2 = 0.0f, c3sq = 0.0f, cdsq = 0.0f, Sf = 0.0f;
+  float R2 = 0.0f, c3sq = 0.0f, cdsq = 0.0f, Sfh = 0.0f;
   float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // eye (cached: the table is not provably read-only)
   int N = 1;
   bool n_is_1 = false;
@@ -170,9 +170,12 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
     // takes the slow path, which runs first: it never leaves a lane that would pass
     // the fast test (it sets k past the march or idles the lane), so the fast test
     // after it picks exactly the lanes it would have picked before.
-    const bool slow = !(esc && k < Sf) && (esc || (int)(trip - dl) >= 0);
+    // Each test is one select and one compare (k is integer-valued, so k >= S is
+    // k - (S - 0.5) >= 0): no scalar mask arithmetic on the hot path.
+    const float kq = k - Sfh;
+    const float xs = esc ? kq : (float)(int)(trip - dl);
 
-    if (slow) {
+    if (xs >= 0.0f) {
       const KParams &P = F->P;
       // (recomputed from an opaque copy: a shared compare would run on every trip)
       float n2c = n2;
@@ -268,7 +271,8 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
       }
     }
 
-    if (esc && k < Sf) {
+    const float xf = esc ? kq : 1.0f;
+    if (xf < 0.0f) {
       if (COUNT) it_lane += (uint32_t)N - (dl - trip);
       k += 1.0f;
       const float t = fmaf(k, dt, t0);
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           ex = uniform_f(F->P.eye[0]);
           ey = uniform_f(F->P.eye[1]);
           ez = uniform_f(F->P.eye[2]);
-          Sf = uniform_f((float)F->P.S);
+          Sfh = uniform_f((float)F->P.S - 0.5f);
           c3sq = uniform_f(c[3] * c[3]);
           cdsq = NORM == 0 ? uniform_f(fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))))
                            : 0.0f;

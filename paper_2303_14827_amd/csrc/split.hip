@@ -36,6 +36,21 @@ struct DQH {
 };
 
 __device__ __forceinline__ h2 hfma(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }
+// Smaller of the two halves (one SDWA instruction; the values here are never NaN).
+__device__ __forceinline__ _Float16 min_halves(h2 a) {
+  _Float16 r;
+  asm("v_min_f16_sdwa %0, %1, %1 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:WORD_0 "
+      "src1_sel:WORD_1"
+      : "=v"(r)
+      : "v"(a));
+  return r;
+}
+// min(a, b) for finite operands (no canonicalising instruction in front).
+__device__ __forceinline__ float fmin_raw(float a, float b) {
+  float r;
+  asm("v_min_f32_e32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 // Packed maximum that ignores a NaN operand. Written out because the generic form
 // first canonicalises its loop-carried operand (an extra instruction per update).
 __device__ __forceinline__ h2 hmax_raw(h2 a, h2 b) {
@@ -44,26 +59,13 @@ __device__ __forceinline__ h2 hmax_raw(h2 a, h2 b) {
   return r;
 }
 __device__ __forceinline__ h2 hsplat(float v) { return h2{(_Float16)v, (_Float16)v}; }
-// Two FP32 values rounded to nearest FP16 and packed.
-__device__ __forceinline__ h2 hpack(float lo, float hi) { return h2{(_Float16)lo, (_Float16)hi}; }
-
-// Sample positions of a pair: (k0 D + X, k1 D + X) for three coordinates, each an FP32
-// fused multiply-add rounded to FP16, written straight into the packed halves with the
-// mixed-precision FMA (two instructions per coordinate instead of two FMAs and a
-// conversion). The closing s_nop gives the half-register writes the wait states a
-// dependent read needs.
-__device__ __forceinline__ void pair_points(float k0, float k1, float DX, float DY, float DZ,
-                                            float X0, float Y0, float Z0, h2 &x, h2 &y, h2 &w) {
-  asm("v_fma_mixlo_f16 %[x], %[k0], %[dx], %[x0]\n\t"
-      "v_fma_mixlo_f16 %[y], %[k0], %[dy], %[y0]\n\t"
-      "v_fma_mixlo_f16 %[w], %[k0], %[dz], %[z0]\n\t"
-      "v_fma_mixhi_f16 %[x], %[k1], %[dx], %[x0]\n\t"
-      "v_fma_mixhi_f16 %[y], %[k1], %[dy], %[y0]\n\t"
-      "v_fma_mixhi_f16 %[w], %[k1], %[dz], %[z0]\n\t"
-      "s_nop 1"
-      : [x] "=&v"(x), [y] "=&v"(y), [w] "=&v"(w)
-      : [k0] "v"(k0), [k1] "v"(k1), [dx] "v"(DX), [dy] "v"(DY), [dz] "v"(DZ), [x0] "v"(X0),
-        [y0] "v"(Y0), [z0] "v"(Z0));
+// Two FP32 values rounded to nearest FP16 and packed (written out so the compiler does
+// not fuse the rounding into a mixed-precision FMA, which issues several times slower
+// than an FP32 FMA followed by this conversion on gfx950).
+__device__ __forceinline__ h2 hpack(float lo, float hi) {
+  h2 r;
+  asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(r) : "v"(lo), "v"(hi));
+  return r;
 }
 
 // One packed update of two independent points (one per half), as dq_update.
@@ -308,20 +310,20 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
   for (int q = 0; q < 8; ++q) c[q] = hsplat(0.0f);
   h2 c3sq = hsplat(0.0f), cdsq = hsplat(0.0f);
   _Float16 R2 = 0;
-  float Sf = 0.0f, Sf2 = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  float Sf = 0.0f, Sf2h = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
   int N = 1;
-  bool closed_first = false;
-  // Trip counter, deadlines and their rebasing as in the FP32 marcher: idle lanes hold
-  // a NaN state (the running maximum ignores it) and the deadline 2^32 - 1.
+  bool n_is_1 = false;
+  // Trip counter and deadlines as in the FP32 marcher (wrap-safe compare; idle lanes
+  // hold a NaN state, which the running maximum ignores, and a deadline 2^31 - 1 ahead).
   uint32_t trip = 0;
-  const uint32_t kIdleDl = 0xFFFFFFFFu;
+  const uint32_t kIdleAhead = 0x7FFFFFFFu;
   const h2 kNaN2 = hsplat(__builtin_nanf(""));
 
-  bool busy = false;
+  int busy = 0;   // an int, not a bool: a per-lane flag the compiler keeps in a VGPR
   DQH z;
   z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = kNaN2;
   h2 s = kNaN2, m2 = hsplat(0.0f);
-  uint32_t dl = kIdleDl;
+  uint32_t dl = kIdleAhead;
   int pix = 0;
   // Sample k of the ray is eye + (t0 + k dt) d, computed as k D + X0 with D = dt d and
   // X0 = eye + t0 d (FP32, then rounded to FP16).
@@ -329,94 +331,100 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
   uint32_t cnt_lo = 0, cnt_hi = 0, it_lane = 0;
 
   for (;;) {
-    if (++trip >= 0x80000000u) {   // rebase (every live deadline is >= trip here)
-      asm volatile("" ::: "memory");   // a branch, not per-trip selects
-      trip -= 0x40000000u;
-      if (dl != kIdleDl) dl -= 0x40000000u;
-    }
+    ++trip;
     if (COUNT) {
       cnt_lo += (m2.x <= R2) ? 1u : 0u;
       cnt_hi += (m2.y <= R2) ? 1u : 0u;
     }
     const h2 n2 = pk_update<NORM>(z, s, c);
     m2 = hmax_raw(m2, n2);
-    const bool both = m2.x > R2 && m2.y > R2;
-    const bool done = both || dl <= trip;
-    if (done) {
-      // Fast path: both samples of the pair are outside and more samples follow.
-      const bool fast = both && kp <= Sf2;   // kp + 2 <= S (exact: small integers)
-      if (fast) {
+    // A pair whose samples are both outside moves on to the next pair (fast path)
+    // unless it holds the last sample; a pair that holds the last sample, or one that
+    // reached max_iter with an inside sample, ends the march (slow path, run first:
+    // it leaves the lanes it ends idle, with m2 = 0, so they fail the fast test).
+    // Both tests are one select and one compare each (kp is integer-valued, so
+    // kp > S - 2 is kp - (S - 1.5) >= 0): no scalar mask arithmetic on the hot path.
+    const _Float16 mn = min_halves(m2);
+    const bool both = mn > R2;
+    const float kq = kp - Sf2h;
+    const float xs = both ? kq : (float)(int)(trip - dl);
+    if (xs >= 0.0f) {
+      const bool esc_lo = m2.x > R2;
+      if (both) {
         if (COUNT) it_lane += cnt_lo + cnt_hi;
-        kp += 2.0f;
-        const float k1 = kp + 1.0f;
-        if (AXIS && closed_first) {
-          h2 xh, yh, wh;
-          pair_points(kp, k1, DX, DY, DZ, X0, Y0, Z0, xh, yh, wh);
-          // z_1 of (x, y, w, 0 | 0) in closed form; m2 starts at ||z_1||^2
-          const h2 tx = xh + xh;
-          z.a0 = hfma(-wh, wh, hfma(-yh, yh, hfma(xh, xh, c[0])));
-          z.a1 = hfma(tx, yh, c[1]);
-          z.a2 = hfma(tx, wh, c[2]);
-          z.a3 = c[3];
-          z.b0 = c[4];
-          z.b1 = c[5];
-          z.b2 = c[6];
-          z.b3 = c[7];
-          s = hfma(z.a2, z.a2, hfma(z.a1, z.a1, c3sq));
-          m2 = hfma(z.a0, z.a0, s + cdsq);
-          dl = trip + (uint32_t)N - 1u;
-          if (COUNT) cnt_lo = cnt_hi = 1;
-        } else {
-          const KParams &P = F->P;
-          const float xl = fmaf(kp, DX, X0), xhh = fmaf(k1, DX, X0);
-          const float yl = fmaf(kp, DY, Y0), yhh = fmaf(k1, DY, Y0);
-          const float wl = fmaf(kp, DZ, Z0), whh = fmaf(k1, DZ, Z0);
-          const DQ<float> zl = slice_map<float>(P, xl, yl, wl);
-          const DQ<float> zh = slice_map<float>(P, xhh, yhh, whh);
-#define DQJ_PK(F_) hpack(zl.F_, zh.F_)
-          z.a0 = DQJ_PK(a0);
-          z.a1 = DQJ_PK(a1);
-          z.a2 = DQJ_PK(a2);
-          z.a3 = DQJ_PK(a3);
-          z.b0 = DQJ_PK(b0);
-          z.b1 = DQJ_PK(b1);
-          z.b2 = DQJ_PK(b2);
-          z.b3 = DQJ_PK(b3);
-#undef DQJ_PK
-          s = hfma(z.a3, z.a3, hfma(z.a2, z.a2, z.a1 * z.a1));
-          m2 = hsplat(0.0f);
-          dl = trip + (uint32_t)N;
-          if (COUNT) cnt_lo = cnt_hi = 0;
-        }
-        if (k1 > Sf) {   // the pair's high half is past the last sample (once per ray)
-          asm volatile("" ::: "memory");   // keep this a branch, not selects
-          m2.y = (_Float16)INFINITY;
-          if (COUNT) cnt_hi = 0;
-        }
+        write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+      } else {
+        if (COUNT) it_lane += cnt_lo + (esc_lo ? cnt_hi : 0u);
+        const uint32_t slot = atomicAdd(ctr + 1, 1u);
+        hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, (int32_t)kp + (esc_lo ? 1 : 0), 0u};
       }
-      // The pair ends the march: a miss, or a hit at its first inside sample.
-      if (done && !fast) {
-        const bool esc_lo = m2.x > R2;
-        if (both) {
-          if (COUNT) it_lane += cnt_lo + cnt_hi;
-          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
-        } else {
-          if (COUNT) it_lane += cnt_lo + (esc_lo ? cnt_hi : 0u);
-          const uint32_t slot = atomicAdd(ctr + 1, 1u);
-          hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, (int32_t)kp + (esc_lo ? 1 : 0), 0u};
-        }
-        busy = false;
-        z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = kNaN2;
-        s = kNaN2;
+      busy = 0;
+      z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = kNaN2;
+      s = kNaN2;
+      m2 = hsplat(0.0f);
+      dl = trip + kIdleAhead;
+    }
+    // (the pair's test from before the slow path: the lanes it ended fail it too)
+    const float xf = both ? kq : 1.0f;
+    if (xf < 0.0f) {
+      if (COUNT) it_lane += cnt_lo + cnt_hi;
+      kp += 2.0f;
+      // The high half of the last pair lies past sample S when S is even. Without
+      // counting it is pointed at sample S again (a duplicate cannot change the pair's
+      // first inside sample); counting launches mark it escaped instead, so it adds
+      // no updates.
+      const float k1 = COUNT ? kp + 1.0f : fmin_raw(kp + 1.0f, Sf);
+      if constexpr (AXIS) {
+        const h2 xh = hpack(fmaf(kp, DX, X0), fmaf(k1, DX, X0));
+        const h2 yh = hpack(fmaf(kp, DY, Y0), fmaf(k1, DY, Y0));
+        const h2 wh = hpack(fmaf(kp, DZ, Z0), fmaf(k1, DZ, Z0));
+        // zeta_1 of (x, y, w, 0 | 0) in closed form; m2 starts at ||zeta_1||^2
+        const h2 tx = xh + xh;
+        const h2 a0 = hfma(-wh, wh, hfma(-yh, yh, hfma(xh, xh, c[0])));
+        z.a1 = hfma(tx, yh, c[1]);
+        z.a2 = hfma(tx, wh, c[2]);
+        z.a3 = c[3];
+        z.b0 = c[4];
+        z.b1 = c[5];
+        z.b2 = c[6];
+        z.b3 = c[7];
+        s = hfma(z.a2, z.a2, hfma(z.a1, z.a1, c3sq));
+        m2 = hfma(a0, a0, s + cdsq);
+        // with max_iter 1 the pair is done: a NaN state leaves m2 as it is
+        z.a0 = n_is_1 ? kNaN2 : a0;
+        dl = trip + (uint32_t)(N - 1);
+        if (COUNT) cnt_lo = cnt_hi = 1;
+      } else {
+        const KParams &P = F->P;
+        const float xl = fmaf(kp, DX, X0), xhh = fmaf(k1, DX, X0);
+        const float yl = fmaf(kp, DY, Y0), yhh = fmaf(k1, DY, Y0);
+        const float wl = fmaf(kp, DZ, Z0), whh = fmaf(k1, DZ, Z0);
+        const DQ<float> zl = slice_map<float>(P, xl, yl, wl);
+        const DQ<float> zh = slice_map<float>(P, xhh, yhh, whh);
+#define DQJ_PK(F_) hpack(zl.F_, zh.F_)
+        z.a0 = DQJ_PK(a0);
+        z.a1 = DQJ_PK(a1);
+        z.a2 = DQJ_PK(a2);
+        z.a3 = DQJ_PK(a3);
+        z.b0 = DQJ_PK(b0);
+        z.b1 = DQJ_PK(b1);
+        z.b2 = DQJ_PK(b2);
+        z.b3 = DQJ_PK(b3);
+#undef DQJ_PK
+        s = hfma(z.a3, z.a3, hfma(z.a2, z.a2, z.a1 * z.a1));
         m2 = hsplat(0.0f);
-        dl = kIdleDl;
+        dl = trip + (uint32_t)N;
+        if (COUNT) cnt_lo = cnt_hi = 0;
+      }
+      if (COUNT && k1 > Sf) {
+        m2.y = (_Float16)INFINITY;
+        cnt_hi = 0;
       }
     }
 
-    // ---- hand new rays to idle lanes
-    for (;;) {
-      const uint64_t idle = __builtin_amdgcn_ballot_w64(!busy);
-      if (!idle) break;
+    // ---- hand new rays to idle lanes (one exit, as in the FP32 marcher)
+    uint64_t idle = __builtin_amdgcn_ballot_w64(busy == 0);
+    while (idle) {
       if (!have_tile) {
         if (exhausted) break;
         if (!pending) {
@@ -449,10 +457,10 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           ey = uniform_f(F->P.eye[1]);
           ez = uniform_f(F->P.eye[2]);
           Sf = uniform_f((float)F->P.S);
-          Sf2 = Sf - 2.0f;
+          Sf2h = Sf - 1.5f;
           c3sq = hsplat(cf[3] * cf[3]);
           cdsq = hsplat(NORM == 0 ? cf[4] * cf[4] + cf[5] * cf[5] + cf[6] * cf[6] + cf[7] * cf[7] : 0.0f);
-          closed_first = AXIS && N > 1;
+          n_is_1 = N == 1;
         }
         tile_local = pend_tile - F->tile_begin + F->tile_offset;
         pending = false;
@@ -461,7 +469,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
       }
       const int rank = rank_in(idle);
       const int avail = tile_rays - next_r;
-      if (!busy && rank < avail) {
+      if (busy == 0 && rank < avail) {
         const KParams &P = F->P;
         const int r = next_r + rank;
         const int i = (int)(tile_local % F->tiles_x) * TW + r % TW;
@@ -481,7 +489,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
             DZ = dt * d[2];
             // enter as if the pair (-2, -1) had just escaped: the next trip starts pair 0
             kp = -2.0f;
-            busy = true;
+            busy = 1;
             m2 = hsplat(INFINITY);
             z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = hsplat(0.0f);
             s = hsplat(0.0f);
@@ -495,8 +503,9 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
       const int cntw = __popcll(idle);
       next_r += cntw < avail ? cntw : avail;
       if (next_r >= tile_rays) have_tile = false;
+      idle = __builtin_amdgcn_ballot_w64(busy == 0);
     }
-    if (exhausted && !__builtin_amdgcn_ballot_w64(busy)) break;
+    if (exhausted && !__builtin_amdgcn_ballot_w64(busy != 0)) break;
   }
   if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
 }
