@@ -25,8 +25,42 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Julia iters/sec & % FP32 VALU peak; p50/p99 frame latency served vs plain"
 FLOPS_PER_UPDATE = 52
-FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector (packed) peak
-FP32_UNPACKED_TFLOPS = 78.6       # one FP32 FMA per lane per clock (no packed FP32)
+FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak
+# Measured issue ceiling of v_fmac_f32 with vector-register operands on this GPU (no packed
+# FP32): 2.78 clocks per wave64 instruction at the nominal 2.4 GHz, i.e. 128 flops per
+# 1.158 ns per SIMD x 1024 SIMDs (profiles/gfx950_valu_issue.md).
+FP32_FMAC_ISSUE_TFLOPS = 113.2
+
+# HBM traffic of the timed plain_1024 kernel from two rocprofv3 --pmc runs (FETCH_SIZE and
+# WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB device copy;
+# profiles/render_refill_plain_1024.md). It belongs to the kernel sources it was measured
+# on: bench.py reports it only while their hash is unchanged, else null.
+TRAFFIC_RECORD = {
+    "sources_sha256": "33029dc94e3984dd4522e88b8ae34c75a7375b8993e85c2be60dbcaf9603ea51",
+    "fetch_kib": 63.27, "fetch_factor": 2.0,
+    "write_kib": 37549.26, "write_factor": 1.0,
+}
+TRAFFIC_SOURCES = ["paper_2303_14827_amd/csrc/render_refill.hip", "paper_2303_14827_amd/csrc/dq_device.h",
+                   "paper_2303_14827_amd/csrc/kparams.h", "paper_2303_14827_amd/csrc/launch.h",
+                   "paper_2303_14827_amd/csrc/refill.h", "paper_2303_14827_amd/csrc/runtime_internal.h",
+                   "paper_2303_14827_amd/build.py", "include/dqj.h"]
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """Bytes per launch of the timed kernel, or None if its sources changed since."""
+    r = TRAFFIC_RECORD
+    if sources_sha256() != r["sources_sha256"]:
+        return None
+    return (r["fetch_kib"] * r["fetch_factor"] + r["write_kib"] * r["write_factor"]) * 1024.0
 
 
 def cpu_threads():
@@ -439,12 +473,12 @@ def main():
         "pct_fp32_peak": 100.0 * achieved_tf / FP32_PEAK_TFLOPS,
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP32_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": recorded_traffic() if args.kernel == "refill" else None,
                      "kernel": "render_refill_kernel" if args.kernel == "refill" else
                                "render_direct_kernel",
                      "kernel_ms_per_launch": ev_ms,
                      "flops_per_launch": FLOPS_PER_UPDATE * ialg,
-                     "frac_of_unpacked_fp32": achieved_tf / FP32_UNPACKED_TFLOPS},
+                     "frac_of_measured_fmac_issue": achieved_tf / FP32_FMAC_ISSUE_TFLOPS},
         "ialg_per_step": ialg,
         "ialg_source": "FP64 oracle, tests/golden/ialg_plain_1024.json",
         "gpu_counted_iters_per_step": exec_iters,
