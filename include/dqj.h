@@ -190,7 +190,11 @@ typedef struct dqj_serve_config {
   int64_t epoch_pixels;        /* pixels per epoch (0: 4 Mi); sizes the per-slot scratch */
   double epoch_work;           /* estimated DQ updates per epoch (0: 8e9) */
   dqj_schedule sched;          /* tile/wave schedule (struct_size 0: default) */
+  int32_t policy;              /* DQJ_SERVE_FAIR (0): every active request gets a share of each
+                                  epoch, the rest first come first served; DQJ_SERVE_OLDEST (1):
+                                  epochs are filled oldest request first */
 } dqj_serve_config;
+enum { DQJ_SERVE_FAIR = 0, DQJ_SERVE_OLDEST = 1 };
 
 typedef struct dqj_request_result {
   uint32_t struct_size;        /* = sizeof(dqj_request_result) */

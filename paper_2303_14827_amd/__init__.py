@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libdqj.so")
 OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_BUDGET, E_QUEUE_FULL, E_DEVICE = -1, -2, -3, -4, -5
 E_TIMEOUT, E_CANCELLED, E_UNSUPPORTED, E_STATE = -6, -7, -8, -9
+SERVE_FAIR, SERVE_OLDEST = 0, 1
 
 NORM_EUCLID8, NORM_REALPART = 0, 1
 PREC_FP32, PREC_SPLIT, PREC_FP64 = 0, 1, 2
@@ -96,6 +97,7 @@ class dqj_serve_config(C.Structure):
         ("epoch_pixels", C.c_int64),
         ("epoch_work", C.c_double),
         ("sched", dqj_schedule),
+        ("policy", C.c_int32),
     ]
 
 
@@ -365,7 +367,8 @@ class Server:
     def __init__(self, precision: int = PREC_SPLIT, norm: int = NORM_EUCLID8,
                  hbm_budget_bytes: int = 0, max_inflight: int = 0, max_pending: int = 0,
                  slots: int = 0, epoch_pixels: int = 0, epoch_work: float = 0.0,
-                 count_iters: bool = False, schedule: Optional[dqj_schedule] = None):
+                 count_iters: bool = False, schedule: Optional[dqj_schedule] = None,
+                 policy: int = SERVE_FAIR):
         cfg = dqj_serve_config()
         cfg.struct_size = C.sizeof(dqj_serve_config)
         cfg.hbm_budget_bytes = hbm_budget_bytes
@@ -373,6 +376,7 @@ class Server:
         cfg.precision, cfg.norm, cfg.slots = precision, norm, slots
         cfg.count_iters = 1 if count_iters else 0
         cfg.epoch_pixels, cfg.epoch_work = epoch_pixels, epoch_work
+        cfg.policy = policy
         if schedule is not None:
             cfg.sched = schedule
         h = C.c_void_p()

@@ -91,6 +91,53 @@ __device__ __forceinline__ float dq_update_inplace(DQ<float> &z, float &s, const
   return n2;
 }
 
+
+// The same update with the Julia constant in vector registers. On gfx950 an FP32
+// operation that reads a scalar register issues at about 1.6x the cost of one whose
+// operands are all vector registers, so the hot loop keeps per-lane copies of c.
+__device__ __forceinline__ float dq_update_inplace_v(DQ<float> &z, float &s, const float *c) {
+  float ta, tb, dot, n2;
+  asm("s_nop 1\n\t"
+      "v_add_f32_e32 %[ta], %[a0], %[a0]\n\t"
+      "v_add_f32_e32 %[tb], %[b0], %[b0]\n\t"
+      "v_mul_f32_e32 %[dot], %[a1], %[b1]\n\t"
+      "v_fmac_f32_e32 %[dot], %[a2], %[b2]\n\t"
+      "v_fmac_f32_e32 %[dot], %[a3], %[b3]\n\t"
+      "v_fma_f32 %[b1], %[ta], %[b1], %[c5]\n\t"
+      "v_fmac_f32_e32 %[b1], %[tb], %[a1]\n\t"
+      "v_fma_f32 %[b2], %[ta], %[b2], %[c6]\n\t"
+      "v_fmac_f32_e32 %[b2], %[tb], %[a2]\n\t"
+      "v_fma_f32 %[b3], %[ta], %[b3], %[c7]\n\t"
+      "v_fmac_f32_e32 %[b3], %[tb], %[a3]\n\t"
+      "v_fma_f32 %[b0], %[ta], %[b0], %[c4]\n\t"
+      "v_fmac_f32_e32 %[b0], -2.0, %[dot]\n\t"
+      "v_fma_f32 %[a1], %[ta], %[a1], %[c1]\n\t"
+      "v_fma_f32 %[a2], %[ta], %[a2], %[c2]\n\t"
+      "v_fma_f32 %[a3], %[ta], %[a3], %[c3]\n\t"
+      "v_fma_f32 %[a0], %[a0], %[a0], %[c0]\n\t"
+      "v_sub_f32_e32 %[a0], %[a0], %[s]\n\t"
+      "v_mul_f32_e32 %[s], %[a1], %[a1]\n\t"
+      "v_fmac_f32_e32 %[s], %[a2], %[a2]\n\t"
+      "v_fmac_f32_e32 %[s], %[a3], %[a3]\n\t"
+      "v_fma_f32 %[n2], %[a0], %[a0], %[s]\n\t"
+      "v_fmac_f32_e32 %[n2], %[b0], %[b0]\n\t"
+      "v_fmac_f32_e32 %[n2], %[b1], %[b1]\n\t"
+      "v_fmac_f32_e32 %[n2], %[b2], %[b2]\n\t"
+      "v_fmac_f32_e32 %[n2], %[b3], %[b3]"
+      : [a0] "+v"(z.a0), [a1] "+v"(z.a1), [a2] "+v"(z.a2), [a3] "+v"(z.a3), [b0] "+v"(z.b0),
+        [b1] "+v"(z.b1), [b2] "+v"(z.b2), [b3] "+v"(z.b3), [s] "+v"(s), [ta] "=&v"(ta),
+        [tb] "=&v"(tb), [dot] "=&v"(dot), [n2] "=&v"(n2)
+      : [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]), [c4] "v"(c[4]),
+        [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7]));
+  return n2;
+}
+// A wave-uniform value copied into a vector register (opaque to the compiler, which
+// would otherwise keep a uniform value in a scalar register).
+__device__ __forceinline__ float to_vgpr(float x) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
 // Hot-loop update: the in-place form for FP32 with the 8-square norm.
 template <int NORM, typename T>
 __device__ __forceinline__ T dq_update_hot(DQ<T> &z, T &s, const T *c) {

@@ -136,6 +136,12 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
   for (int q = 0; q < 8; ++q) c[q] = 0.0f;
   float R2 = 0.0f, c3sq = 0.0f, cdsq = 0.0f, Sfh = 0.0f;
   float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // eye (cached: the table is not provably read-only)
+  // Per-lane copies of c: the update and the closed-form start compute with vector
+  // registers only (scalar-register operands cost more issue time on gfx950). The eye,
+  // S - 1/2 and c3^2 below are per-lane copies for the same reason.
+  float cv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) cv[q] = 0.0f;
   int N = 1;
   bool n_is_1 = false;
   // Trip counter: one update per trip. A point started in trip t has had trip - t
@@ -163,7 +169,11 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
   for (;;) {
     ++trip;
     // ---- one update on every lane
-    const float n2 = dq_update_hot<NORM>(z, s, c);
+    float n2;
+    if constexpr (NORM == 0)
+      n2 = dq_update_inplace_v(z, s, cv);
+    else
+      n2 = dq_update<NORM>(z, s, cv);
     const bool esc = n2 > R2;
     // Fast path: an outside march sample with more samples to go starts the next one.
     // Everything else that retires (a march hit or miss, a bisection or normal point)
@@ -283,14 +293,14 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
         // First update in closed form: zeta_0 = (x, y, w, 0 | 0) gives
         // zeta_1 = (x^2 - y^2 - w^2 + c0, 2xy + c1, 2xw + c2, c3 | c_d).
         const float tx = x + x;
-        float a0 = fmaf(-w, w, fmaf(-y, y, fmaf(x, x, c[0])));
-        z.a1 = fmaf(tx, y, c[1]);
-        z.a2 = fmaf(tx, w, c[2]);
-        z.a3 = c[3];
-        z.b0 = c[4];
-        z.b1 = c[5];
-        z.b2 = c[6];
-        z.b3 = c[7];
+        float a0 = fmaf(-w, w, fmaf(-y, y, fmaf(x, x, cv[0])));
+        z.a1 = fmaf(tx, y, cv[1]);
+        z.a2 = fmaf(tx, w, cv[2]);
+        z.a3 = cv[3];
+        z.b0 = cv[4];
+        z.b1 = cv[5];
+        z.b2 = cv[6];
+        z.b3 = cv[7];
         s = fmaf(z.a2, z.a2, fmaf(z.a1, z.a1, c3sq));
         if constexpr (STICKY) {
           // zeta_2 escapes whenever zeta_1 does: leave zeta_1 untested (a sample that
@@ -336,15 +346,18 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
           frame = f;
           if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) c[q] = uniform_f(F->P.c[q]);
+          for (int q = 0; q < 8; ++q) {
+            c[q] = uniform_f(F->P.c[q]);
+            cv[q] = to_vgpr(c[q]);
+          }
           R2 = uniform_f(F->P.R2);
           N = (int)uniform((uint32_t)F->P.N);
           n_is_1 = N == 1;
-          ex = uniform_f(F->P.eye[0]);
-          ey = uniform_f(F->P.eye[1]);
-          ez = uniform_f(F->P.eye[2]);
-          Sfh = uniform_f((float)F->P.S - 0.5f);
-          c3sq = uniform_f(c[3] * c[3]);
+          ex = to_vgpr(uniform_f(F->P.eye[0]));
+          ey = to_vgpr(uniform_f(F->P.eye[1]));
+          ez = to_vgpr(uniform_f(F->P.eye[2]));
+          Sfh = to_vgpr(uniform_f((float)F->P.S - 0.5f));
+          c3sq = to_vgpr(uniform_f(c[3] * c[3]));
           cdsq = NORM == 0 ? uniform_f(fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))))
                            : 0.0f;
         }

@@ -241,6 +241,8 @@ dqj_status dqj_serve_create(const dqj_serve_config *cfg, dqj_server **out) {
   if (cfg->max_inflight < 0 || cfg->max_pending < 0 || cfg->epoch_pixels < 0 ||
       !(cfg->epoch_work >= 0))
     return fail(DQJ_E_INVALID, "negative limits in the server config");
+  if (cfg->policy != DQJ_SERVE_FAIR && cfg->policy != DQJ_SERVE_OLDEST)
+    return fail(DQJ_E_INVALID, "policy must be one of DQJ_SERVE_*");
   if (cfg->sched.struct_size != 0 && cfg->sched.struct_size != sizeof(dqj_schedule))
     return fail(DQJ_E_INVALID, "config.sched.struct_size must be 0 or sizeof(dqj_schedule)");
   int dev = 0, cus = 0;
@@ -252,6 +254,7 @@ dqj_status dqj_serve_create(const dqj_serve_config *cfg, dqj_server **out) {
   if (cfg->max_pending) cc.max_pending = cfg->max_pending;
   if (cfg->epoch_pixels) cc.epoch_pixels = (uint64_t)cfg->epoch_pixels;
   if (cfg->epoch_work > 0) cc.epoch_work = cfg->epoch_work;
+  cc.oldest_first = cfg->policy == DQJ_SERVE_OLDEST;
   dqj_server *s = nullptr;
   try {
     s = new dqj_server(cc);

@@ -97,12 +97,14 @@ bool Core::build_epoch(double now, Epoch *out) {
     pix_left -= n * r.spec.tile_pixels;
     e.pixels += n * r.spec.tile_pixels;
   };
-  // pass 1: an equal share of the epoch for every request (at least one tile each,
-  // so no request waits for another to drain)
-  const double share = cfg_.epoch_work / (double)cand.size();
-  for (uint64_t t : cand) {
-    const RequestInfo &r = reqs_.at(t);
-    take(t, std::max(share, r.spec.work_per_tile));
+  // pass 1 (fair policy): an equal share of the epoch for every request (at least one
+  // tile each, so no request waits for another to drain)
+  if (!cfg_.oldest_first) {
+    const double share = cfg_.epoch_work / (double)cand.size();
+    for (uint64_t t : cand) {
+      const RequestInfo &r = reqs_.at(t);
+      take(t, std::max(share, r.spec.work_per_tile));
+    }
   }
   // pass 2: what is left of the epoch, first come first served
   for (uint64_t t : cand) {

@@ -39,6 +39,7 @@ struct CoreConfig {
   double epoch_work = 8e9;             // estimated DQ updates per epoch
   uint64_t epoch_pixels = 4u << 20;    // pixels per epoch (scratch capacity)
   int32_t max_chunks = 256;            // table entries per epoch
+  bool oldest_first = false;           // fill epochs oldest request first (no fair share)
 };
 
 struct RequestSpec {

@@ -12,8 +12,9 @@ using namespace dqj::serve;
 extern "C" {
 
 void *core_new(uint64_t budget, int32_t max_inflight, int32_t max_pending, double epoch_work,
-               uint64_t epoch_pixels, int32_t max_chunks) {
+               uint64_t epoch_pixels, int32_t max_chunks, int32_t oldest_first) {
   CoreConfig c;
+  c.oldest_first = oldest_first != 0;
   c.budget_bytes = budget;
   c.max_inflight = max_inflight;
   c.max_pending = max_pending;

@@ -24,7 +24,8 @@ def L(tmp_path_factory):
                     "-o", so], check=True)
     lib = C.CDLL(so)
     lib.core_new.restype = C.c_void_p
-    lib.core_new.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.c_int32]
+    lib.core_new.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.c_int32,
+                             C.c_int32]
     lib.core_free.argtypes = [C.c_void_p]
     lib.core_submit.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_double, C.c_double,
                                 C.POINTER(C.c_uint64)]
@@ -43,9 +44,10 @@ def L(tmp_path_factory):
 
 class Core:
     def __init__(self, L, budget=1000, max_inflight=64, max_pending=100, epoch_work=100.0,
-                 epoch_pixels=1 << 20, max_chunks=256):
+                 epoch_pixels=1 << 20, max_chunks=256, oldest_first=False):
         self.L = L
-        self.h = L.core_new(budget, max_inflight, max_pending, epoch_work, epoch_pixels, max_chunks)
+        self.h = L.core_new(budget, max_inflight, max_pending, epoch_work, epoch_pixels, max_chunks,
+                            1 if oldest_first else 0)
 
     def submit(self, nbytes, tiles, now=0.0, tile_px=64, wpt=1.0):
         t = C.c_uint64()
@@ -157,6 +159,25 @@ def test_every_tile_once_and_fair_share(L):
             nxt += n
         c.finish(e[0], True, 3.0)
     assert nxt == 1000 and c.state(big)[0] == DONE
+
+
+def test_oldest_first_policy(L):
+    # epochs are filled oldest request first: a newcomer waits until the older request's
+    # remaining tiles fit, then shares the epoch with it
+    c = Core(L, epoch_work=100.0, oldest_first=True)
+    _, big = c.submit(1, 250)
+    _, small = c.submit(1, 5)
+    c.admit()
+    eid, ch = c.build()
+    assert ch == [(big, 0, 100)]
+    c.finish(eid, True, 1.0)
+    eid, ch = c.build(1.0)
+    assert ch == [(big, 100, 100)]
+    c.finish(eid, True, 2.0)
+    eid, ch = c.build(2.0)
+    assert ch == [(big, 200, 50), (small, 0, 5)]
+    fin = c.finish(eid, True, 3.0)
+    assert set(fin) == {big, small}
 
 
 def test_pixel_and_chunk_caps(L):
