@@ -348,6 +348,61 @@ def bench_sweep(args, dqj, workloads, torch):
     }
 
 
+def bench_de(args, dqj, workloads, torch):
+    """plain_1024's three frames marched by distance estimates (FP32, one-thread-per-pixel
+    kernel, one dqj_render per frame), against the FP64 oracle's count of the updates that
+    march runs (tests/golden/ialg_de_1024.json). Each DE update also carries the derivative
+    norm: 2 more flops than the fixed march's 52."""
+    import numpy as np
+    ps = workloads.de_1024()
+    with open(os.path.join(ROOT, "tests", "golden", "ialg_de_1024.json")) as f:
+        ialg = json.load(f)["total_iters"]
+    stream = torch.cuda.current_stream()
+    outs = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
+    for p, o in zip(ps, outs):
+        dqj.render(p, out=o, stream=stream)
+    torch.cuda.synchronize()
+    counted = sum(int(o["iters"].item()) for o in outs)
+    timed = [{k: v for k, v in o.items() if k != "iters"} for o in outs]
+    for _ in range(args.warmup):
+        for p, o in zip(ps, timed):
+            dqj.render(p, out=o, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        for p, o in zip(ps, timed):
+            dqj.render(p, out=o, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    flops = FLOPS_PER_UPDATE + 2
+    achieved = flops * ialg / (ev_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": ialg / (ms * 1e-3), "unit": "Julia iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "de_1024: plain_1024's 3 frames marched by distance estimates "
+                               "(at most 512 steps, hit below 1e-4, steps in [1e-4, 0.25], "
+                               "10 bisection steps), one dqj_render per frame",
+                   "frames": 3, "width": 1024, "height": 1024, "max_iter": 24},
+        "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "render_de_kernel", "kernel_ms_per_step": ev_ms,
+                     "flops_per_update": flops},
+        "ialg_per_step": ialg, "ialg_source": "FP64 oracle, tests/golden/ialg_de_1024.json",
+        "gpu_counted_iters_per_step": counted,
+        "hits_per_frame": [int(o["mask"].sum().item()) for o in outs],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,7 +415,7 @@ def main():
                     help="length of the served request stream (0: skip; the full stream is 60)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--capacity-requests", type=int, default=300)
-    ap.add_argument("--workload", choices=["plain_1024", "split_1080p", "sweep_256"],
+    ap.add_argument("--workload", choices=["plain_1024", "split_1080p", "sweep_256", "de_1024"],
                     default="plain_1024")
     ap.add_argument("--error-pixels", type=int, default=4000)
     ap.add_argument("--sweep-frames", type=int, default=4096)
@@ -389,7 +444,7 @@ def main():
 
     if args.workload != "plain_1024":
         torch.cuda.set_device(0)
-        fn = bench_split if args.workload == "split_1080p" else bench_sweep
+        fn = {"split_1080p": bench_split, "sweep_256": bench_sweep, "de_1024": bench_de}[args.workload]
         print(json.dumps(fn(args, dqj, workloads, torch)), flush=True)
         return
 

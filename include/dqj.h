@@ -86,7 +86,19 @@ typedef struct dqj_params {
   double normal_h;             /* central-difference step, > 0 */
   double light_dir[3];         /* direction towards the light (normalised by the library) */
   double k_ambient, k_diffuse;
+  /* March mode (section "Ray-Marching"). FIXED: the S-step march above, then bisection.
+   * DE: steps of the distance estimate 0.5 |z_m| ln|z_m| / |z'_m| (Eq. distfract2), with
+   * |z'_{n+1}| = 2 |z_n| |z'_n| and |z'_0| = 1 (Eq. distfract; norms are the escape norm),
+   * clamped to [de_min_step, de_max_step]; a hit when the estimate drops below de_hit_eps,
+   * or, if a step lands inside the set, the bisection of that step; at most S steps.
+   * DE renders run in FP32 through dqj_render only. */
+  int32_t march;               /* DQJ_MARCH_FIXED (0) or DQJ_MARCH_DE (1) */
+  double de_hit_eps;           /* DE: > 0, world units */
+  double de_min_step;          /* DE: > 0 */
+  double de_max_step;          /* DE: >= de_min_step */
 } dqj_params;
+
+enum { DQJ_MARCH_FIXED = 0, DQJ_MARCH_DE = 1 };
 
 /* Per-pixel ray flags written to dqj_frame_out.flags (bit set). */
 enum {

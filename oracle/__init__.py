@@ -43,6 +43,10 @@ class _Params(C.Structure):
         ("light_dir", C.c_double * 3),
         ("k_ambient", C.c_double),
         ("k_diffuse", C.c_double),
+        ("march", C.c_int32),
+        ("de_hit_eps", C.c_double),
+        ("de_min_step", C.c_double),
+        ("de_max_step", C.c_double),
     ]
 
 
@@ -69,6 +73,8 @@ def lib():
         L.dqjo_classify.restype = C.c_int32
         L.dqjo_classify_many.argtypes = [P, D, C.c_int64, C.POINTER(C.c_uint8),
                                          C.POINTER(C.c_int32), D, D]
+        L.dqjo_distance.argtypes = [P, D, C.POINTER(C.c_int32), D]
+        L.dqjo_distance.restype = C.c_int32
         L.dqjo_slice_map.argtypes = [P, D, D]
         L.dqjo_ray.argtypes = [P, C.c_int32, C.c_int32, D, D, D, D]
         L.dqjo_ray.restype = C.c_int32
@@ -106,6 +112,10 @@ def make_params(p) -> _Params:
     s.normal_h = p.normal_h
     s.light_dir[:] = list(p.light_dir)
     s.k_ambient, s.k_diffuse = p.k_ambient, p.k_diffuse
+    s.march = getattr(p, "march", 0)
+    s.de_hit_eps = getattr(p, "de_hit_eps", 1e-4)
+    s.de_min_step = getattr(p, "de_min_step", 1e-4)
+    s.de_max_step = getattr(p, "de_max_step", 0.25)
     return s
 
 
@@ -167,6 +177,23 @@ def classify(p, points) -> Dict[str, np.ndarray]:
                              inside.ctypes.data_as(C.POINTER(C.c_uint8)),
                              m.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(n2), _dptr(zf))
     return {"inside": inside, "m": m, "norm2": n2, "zfinal": zf}
+
+
+def distance(p, points) -> Dict[str, np.ndarray]:
+    """Distance estimate of points of R^8 (shape (n, 8)): inside, m, de (0 when inside)."""
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 8))
+    n = pts.shape[0]
+    inside = np.zeros(n, np.uint8)
+    m = np.zeros(n, np.int32)
+    de = np.zeros(n)
+    sp = make_params(p)
+    for q in range(n):
+        mi = C.c_int32()
+        d = np.zeros(1)
+        inside[q] = lib().dqjo_distance(C.byref(sp), _dptr(pts[q]), C.byref(mi), _dptr(d))
+        m[q] = mi.value
+        de[q] = d[0]
+    return {"inside": inside, "m": m, "de": de}
 
 
 def slice_map(p, x) -> np.ndarray:

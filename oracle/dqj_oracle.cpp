@@ -127,6 +127,33 @@ int32_t dqjo_classify(const dqjo_params *p, const double z0[8], int32_t *m,
   return inside;
 }
 
+// Distance estimate (section "Ray-Marching", Eq. distfract2 after Hart et al.):
+// iterate as dqjo_classify while carrying the derivative norm of Eq. distfract, read
+// as |z'_{n+1}| = 2 |z_n| |z'_n| with |z'_0| = 1 (the printed indices are garbled); the
+// norms are the escape norm. For a point that escapes at m the estimate is
+// 0.5 |z_m| ln|z_m| / |z'_m|. Returns 1 for an inside point (no estimate).
+int32_t dqjo_distance(const dqjo_params *p, const double z0[8], int32_t *m, double *de) {
+  const double R2 = p->escape_radius * p->escape_radius;
+  double z[8];
+  memcpy(z, z0, sizeof z);
+  double n2 = escape_norm2(p, z);     // |z_0|^2
+  double dz = 1.0;                    // |z'_0|
+  for (int32_t n = 1; n <= p->max_iter; ++n) {
+    dz = 2.0 * sqrt(n2) * dz;         // |z'_n| from |z_{n-1}| and |z'_{n-1}|
+    dq_step(z, p->c, z);
+    n2 = escape_norm2(p, z);
+    if (n2 > R2) {
+      const double r = sqrt(n2);
+      if (m) *m = n;
+      if (de) *de = 0.5 * r * log(r) / dz;
+      return 0;
+    }
+  }
+  if (m) *m = p->max_iter;
+  if (de) *de = 0.0;
+  return 1;
+}
+
 void dqjo_classify_many(const dqjo_params *p, const double *pts, int64_t n,
                         uint8_t *inside, int32_t *m, double *norm2, double *zfinal) {
 #pragma omp parallel for schedule(dynamic, 256)
@@ -245,31 +272,72 @@ static PixelResult render_pixel(const dqjo_params *p, int32_t i, int32_t j) {
   double o[3], d[3], t0, t1;
   if (!dqjo_ray(p, i, j, o, d, &t0, &t1)) return res;
 
-  // Fixed-step march: S steps over [t0, t1], samples t_k = t0 + k dt, k = 0..S.
   const int32_t S = p->march_steps;
-  const double dt = (t1 - t0) / S;
   int32_t kstar = -1;
-  for (int32_t k = 0; k <= S; ++k) {
-    const double t = t0 + k * dt;
-    const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-    int32_t m;
-    const int32_t in = classify_world(p, x, &m);
-    res.iters += (uint64_t)m;
-    if (in) {
-      kstar = k;
-      break;
+  double thit = t0;
+  double lo = t0, hi = t0;       // bracket to bisect (when bisect is set)
+  int bisect = 0;
+  if (p->march == 1) {
+    // Distance-estimate march (section "Ray-Marching"): from the box entry, step by the
+    // estimate clamped to [min_step, max_step] until it falls below the hit threshold
+    // (hit at this point), a step lands inside the set (bisect that step), the ray
+    // leaves the box, or S steps were taken (miss).
+    double t = t0, tprev = t0;
+    for (int32_t k = 0; k < S; ++k) {
+      const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+      double z0[8], de;
+      int32_t m;
+      dqjo_slice_map(p, x, z0);
+      const int32_t in = dqjo_distance(p, z0, &m, &de);
+      res.iters += (uint64_t)m;
+      if (in) {
+        kstar = k;
+        if (k == 0) {
+          thit = t0;
+        } else {
+          lo = tprev;
+          hi = t;
+          bisect = 1;
+        }
+        break;
+      }
+      if (de < p->de_hit_eps) {
+        kstar = k;
+        thit = t;
+        break;
+      }
+      double step = de < p->de_min_step ? p->de_min_step : de;
+      if (step > p->de_max_step) step = p->de_max_step;
+      tprev = t;
+      t = t + step;
+      if (t > t1) break;
+    }
+  } else {
+    // Fixed-step march: S steps over [t0, t1], samples t_k = t0 + k dt, k = 0..S.
+    const double dt = (t1 - t0) / S;
+    for (int32_t k = 0; k <= S; ++k) {
+      const double t = t0 + k * dt;
+      const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+      int32_t m;
+      const int32_t in = classify_world(p, x, &m);
+      res.iters += (uint64_t)m;
+      if (in) {
+        kstar = k;
+        break;
+      }
+    }
+    // Bisection of the bracket [t_{k*-1}, t_{k*}]; a hit on the first sample has no
+    // outside end to bracket: the hit is t0.
+    if (kstar > 0) {
+      lo = t0 + (kstar - 1) * dt;
+      hi = t0 + kstar * dt;
+      bisect = 1;
     }
   }
   if (kstar < 0) return res;
 
-  // Bisection of the bracket [t_{k*-1}, t_{k*}]; the hit is the final midpoint.
-  // A hit on the first sample has no outside end to bracket: the hit is t0.
-  double thit;
-  if (kstar == 0) {
-    thit = t0;
-  } else {
-    double lo = t0 + (kstar - 1) * dt;
-    double hi = t0 + kstar * dt;
+  // Bisection: the hit is the final midpoint (B = 0: the midpoint of the bracket).
+  if (bisect) {
     for (int32_t b = 0; b < p->bisect_steps; ++b) {
       const double tm = 0.5 * (lo + hi);
       const double x[3] = {o[0] + tm * d[0], o[1] + tm * d[1], o[2] + tm * d[2]};

@@ -48,6 +48,8 @@ typedef struct dqjo_params {
   double normal_h;
   double light_dir[3];
   double k_ambient, k_diffuse;
+  int32_t march;               /* 0: fixed steps, 1: distance-estimate steps */
+  double de_hit_eps, de_min_step, de_max_step;
 } dqjo_params;
 
 /* ---- algebra (Appendix) ---- */
@@ -67,6 +69,10 @@ int32_t dqjo_classify(const dqjo_params *p, const double z0[8], int32_t *m,
                       double zfinal[8], double *norm2);
 
 /* Batched classify over n points (row-major n x 8). Outputs may be NULL. */
+/* Distance estimate 0.5 |z_m| ln|z_m| / |z'_m| of a point that escapes at m, with
+ * |z'_{n+1}| = 2 |z_n| |z'_n|, |z'_0| = 1 (section "Ray-Marching", Eq. distfract,
+ * Eq. distfract2). Returns 1 (and *de = 0) for an inside point. */
+int32_t dqjo_distance(const dqjo_params *p, const double z0[8], int32_t *m, double *de);
 void dqjo_classify_many(const dqjo_params *p, const double *pts, int64_t n,
                         uint8_t *inside, int32_t *m, double *norm2, double *zfinal);
 

@@ -18,6 +18,7 @@ OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_BUDGET, E_QUEUE_FULL, E_DEVICE = -1, -2, -3, -4, -5
 E_TIMEOUT, E_CANCELLED, E_UNSUPPORTED, E_STATE = -6, -7, -8, -9
 SERVE_FAIR, SERVE_OLDEST = 0, 1
+MARCH_FIXED, MARCH_DE = 0, 1
 
 NORM_EUCLID8, NORM_REALPART = 0, 1
 PREC_FP32, PREC_SPLIT, PREC_FP64 = 0, 1, 2
@@ -56,6 +57,10 @@ class dqj_params(C.Structure):
         ("light_dir", C.c_double * 3),
         ("k_ambient", C.c_double),
         ("k_diffuse", C.c_double),
+        ("march", C.c_int32),
+        ("de_hit_eps", C.c_double),
+        ("de_min_step", C.c_double),
+        ("de_max_step", C.c_double),
     ]
 
 
@@ -227,6 +232,10 @@ def make_params(p) -> dqj_params:
     s.normal_h = p.normal_h
     s.light_dir[:] = list(p.light_dir)
     s.k_ambient, s.k_diffuse = p.k_ambient, p.k_diffuse
+    s.march = getattr(p, "march", 0)
+    s.de_hit_eps = getattr(p, "de_hit_eps", 1e-4)
+    s.de_min_step = getattr(p, "de_min_step", 1e-4)
+    s.de_max_step = getattr(p, "de_max_step", 0.25)
     return s
 
 

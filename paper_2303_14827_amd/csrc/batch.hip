@@ -40,6 +40,8 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
     st = validate_out(outs + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
+    if (params[i].march != DQJ_MARCH_FIXED)
+      return fail(DQJ_E_UNSUPPORTED, "frame %d: the distance-estimate march runs through dqj_render", i);
     if (params[i].precision != DQJ_PREC_FP32 && params[i].precision != DQJ_PREC_SPLIT)
       return fail(DQJ_E_UNSUPPORTED, "frame %d: batched renders run in FP32 or split precision", i);
     if (i > 0 && params[i].precision != params[0].precision)

@@ -35,7 +35,12 @@ struct alignas(16) KParams {
   int32_t fp64_window;   // split precision verify window
   int32_t sticky1;       // 1 if, on the identity slice, escaping on the first update
                          // implies escaping on the second (see pack_params)
-  int32_t pad;
+  int32_t march;         // 0: fixed steps, 1: distance-estimate steps
+  float de_eps;          // DE march: hit threshold
+  float de_min_step, de_max_step;
+  float de_inv_r2;       // 1 / R^2 (the scaled derivative norm, see render_de.hip)
+  float de_log2_4r2;     // log2(4 R^2)
+  int32_t pad2[2];
 };
 static_assert(sizeof(KParams) % 16 == 0, "KParams must be 16-byte sized");
 

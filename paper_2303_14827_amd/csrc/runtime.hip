@@ -124,6 +124,15 @@ dqj_status validate_params(const dqj_params *p) {
   if (p->precision != DQJ_PREC_FP32 && p->precision != DQJ_PREC_SPLIT &&
       p->precision != DQJ_PREC_FP64)
     return fail(DQJ_E_INVALID, "precision must be one of DQJ_PREC_*");
+  if (p->march != DQJ_MARCH_FIXED && p->march != DQJ_MARCH_DE)
+    return fail(DQJ_E_INVALID, "march must be one of DQJ_MARCH_*");
+  if (p->march == DQJ_MARCH_DE) {
+    if (!(p->de_hit_eps > 0.0 && std::isfinite(p->de_hit_eps)) ||
+        !(p->de_min_step > 0.0 && std::isfinite(p->de_min_step)) ||
+        !(p->de_max_step >= p->de_min_step && std::isfinite(p->de_max_step)))
+      return fail(DQJ_E_INVALID,
+                  "DE march needs de_hit_eps > 0 and 0 < de_min_step <= de_max_step, finite");
+  }
   if (p->precision == DQJ_PREC_SPLIT && (p->fp64_window < 1 || p->fp64_window > 8))
     return fail(DQJ_E_INVALID, "fp64_window must be in 1..8 for split precision");
   if (p->precision == DQJ_PREC_SPLIT && !(p->escape_radius * p->escape_radius < 65504.0))
@@ -208,6 +217,12 @@ void pack_params(const dqj_params &p, KParams &k) {
   k.B = p.bisect_steps;
   k.norm = p.norm;
   k.fp64_window = p.fp64_window;
+  k.march = p.march;
+  k.de_eps = (float)p.de_hit_eps;
+  k.de_min_step = (float)p.de_min_step;
+  k.de_max_step = (float)p.de_max_step;
+  k.de_inv_r2 = (float)(1.0 / (p.escape_radius * p.escape_radius));
+  k.de_log2_4r2 = (float)std::log2(4.0 * p.escape_radius * p.escape_radius);
   // On the identity slice zeta_0 = (x, y, z, 0 | 0), so zeta_1 = (a | c_d) with a real
   // quaternion a. If zeta_1 escapes, |a|^2 > R^2 - |c_d|^2 (8 squares) or > R^2 (real
   // part). The real part of zeta_2 is a^2 + c_r and the quaternion norm is
@@ -405,6 +420,13 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
   pack_params(*params, kp);
   const KOut ko = to_kout(*out);
   hipError_t e;
+  if (params->march == DQJ_MARCH_DE) {
+    if (params->precision != DQJ_PREC_FP32)
+      return fail(DQJ_E_UNSUPPORTED, "the distance-estimate march runs in FP32 only");
+    e = launch_render_de(kp, ko, stream);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return DQJ_OK;
+  }
   switch (params->precision) {
     case DQJ_PREC_FP32:
       e = launch_render_fp32(kp, ko, pick_schedule(sched, *params, cus), cus, stream);

@@ -304,6 +304,8 @@ dqj_status dqj_serve_submit(dqj_server *s, const dqj_params *params, const dqj_f
                 params->precision, s->precision);
   if (params->norm != s->norm)
     return fail(DQJ_E_INVALID, "request norm differs from the server's");
+  if (params->march != DQJ_MARCH_FIXED)
+    return fail(DQJ_E_UNSUPPORTED, "the server runs the fixed-step march");
   Record rec;
   memset(&rec.frame, 0, sizeof rec.frame);
   pack_params(*params, rec.frame.P);

@@ -6,7 +6,11 @@ per frame (march samples through the first inside one, bisection, 6 normal sampl
 each to escape or max_iter), plus hit counts. The benchmark divides this count by
 the GPU time to report Julia iterations per second.
 
-Run:  python tests/golden/make_golden.py
+ialg_de_1024.json: the same for the same three frames marched by distance estimates
+(at most 512 steps, hit below 1e-4, steps clamped to [1e-4, 0.25], 10 bisection steps
+when a step lands inside).
+
+Run:  python tests/golden/make_golden.py [plain|de]
 """
 import json
 import os
@@ -20,22 +24,26 @@ import oracle      # noqa: E402
 import workloads   # noqa: E402
 
 
-def main():
+def main(which):
     frames = []
     t = time.time()
-    for seed, p in zip((0, 1, 2), workloads.plain_1024()):
+    ps = workloads.plain_1024() if which == "plain" else workloads.de_1024()
+    for seed, p in zip((0, 1, 2), ps):
         r = oracle.render(p)
         frames.append({"seed": seed, "c": p.c, "iters": r["total_iters"],
                        "hits": int(r["mask"].sum())})
         print(frames[-1], flush=True)
-    out = {"workload": "plain_1024", "width": 1024, "height": 1024, "max_iter": 24,
+    out = {"workload": f"{which}_1024", "width": 1024, "height": 1024, "max_iter": 24,
            "march_steps": 512, "bisect_steps": 10, "frames": frames,
            "total_iters": sum(f["iters"] for f in frames),
            "generator": "tests/golden/make_golden.py (FP64 oracle)",
            "oracle_seconds": round(time.time() - t, 1)}
-    with open(os.path.join(HERE, "ialg_plain_1024.json"), "w") as f:
+    if which == "de":
+        out.update({"march": "distance estimate", "de_hit_eps": ps[0].de_hit_eps,
+                    "de_min_step": ps[0].de_min_step, "de_max_step": ps[0].de_max_step})
+    with open(os.path.join(HERE, f"ialg_{which}_1024.json"), "w") as f:
         json.dump(out, f, indent=1)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "plain")

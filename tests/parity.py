@@ -70,7 +70,22 @@ def compare(p, gpu: Dict[str, np.ndarray], ora: Dict[str, np.ndarray],
         rep["shade_err_p999"] = 0.0
     # mismatch diagnosis: the disputed sample must sit within one march step of a class change
     far = []
-    if scan and "first_hit" in g:
+    if scan and getattr(p, "march", workloads.MARCH_FIXED) == workloads.MARCH_DE:
+        # Distance-estimate march: the disputed point is the nearer of the two hits; the
+        # ray must pass close to the set there (inside, or an FP64 estimate below 10 eps)
+        for q in mism[:max_scan]:
+            pix = int(idx[q])
+            i, j = pix % p.width, pix // p.width
+            hit, o3, d3, t0, t1 = oracle.ray(p, i, j)
+            ts = [float(t) for t in (g["depth"][q], o["depth"][q]) if np.isfinite(t)]
+            if not hit or not ts:
+                far.append(pix)
+                continue
+            x = np.asarray(o3) + min(ts) * np.asarray(d3)
+            dd = oracle.distance(p, oracle.slice_map(p, x).reshape(1, 8))
+            if not (dd["inside"][0] or dd["de"][0] < 10.0 * p.de_hit_eps):
+                far.append(pix)
+    elif scan and "first_hit" in g:
         for q in mism[:max_scan]:
             pix = int(idx[q])
             i, j = pix % p.width, pix // p.width

@@ -1,0 +1,114 @@
+"""GPU distance-estimate march (FP32) against the FP64 oracle's DE march, and the
+c = 0 closed form: every hit bisected onto the ball of radius R^(2^-N).
+
+Mask and depth meet the plain path's bar. Shading is held to 99% of agreeing hits
+within 1/255 (DE_SHADE_FRAC): a DE hit is where a chaotic estimate first drops below the
+threshold, so the FP32 and FP64 marches can stop one step apart (within the depth
+tolerance), which shifts the normal's stencil in dust-like parts of the set."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from parity import assert_parity, compare, sample_pixels, to_numpy
+
+pytestmark = pytest.mark.gpu
+DE_SHADE_FRAC = 0.99
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dqj():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2303_14827_amd as m
+    m.lib()
+    return m
+
+
+def render(dqj, p):
+    import torch
+    o = dqj.render(p)
+    torch.cuda.synchronize()
+    return to_numpy(o)
+
+
+def test_de_c0_closed_form(dqj):
+    from test_oracle_render import analytic_ball
+    import oracle
+    N, B = 12, 8
+    p = workloads.Params(c=[0.0] * 8, width=48, height=48, max_iter=N, march_steps=400,
+                         bisect_steps=B, march=workloads.MARCH_DE)
+    g = render(dqj, p)
+    rho = 4.0 ** (2.0 ** -N)
+    n = 0
+    for j in range(p.height):
+        for i in range(p.width):
+            hit, o, d, t0, t1 = oracle.ray(p, i, j)
+            tstar, chord = analytic_ball(o, d, rho)
+            if tstar is None:
+                assert g["mask"][j, i] == 0
+                continue
+            if chord < 1e-2:
+                continue
+            assert g["mask"][j, i] == 1, (i, j)
+            assert abs(float(g["depth"][j, i]) - tstar) <= 2.5e-4 * 2.0 ** -B + 2e-6, (i, j)
+            n += 1
+    say("c0 hits checked", n)
+    assert n > 400
+
+
+@pytest.mark.parametrize("norm", [workloads.NORM_EUCLID8, workloads.NORM_REALPART])
+def test_de_128_full_frame(dqj, norm):
+    import oracle
+    p = workloads.de_128()[0].replace(norm=norm)
+    g = render(dqj, p)
+    o = oracle.render(p)
+    rep = compare(p, g, o)
+    say(norm, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+    assert rep["hits_oracle"] > 300
+    assert_parity(rep, 0.999, DE_SHADE_FRAC)
+
+
+def test_de_1024_sampled(dqj):
+    import oracle
+    p = workloads.de_1024()[2]
+    g = render(dqj, p)
+    pix = sample_pixels(p, 2500, 3)
+    hits = np.nonzero(g["mask"].reshape(-1))[0]
+    pix = np.union1d(pix, np.random.default_rng(4).choice(hits, 1500, replace=False))
+    o = oracle.render(p, pixels=pix)
+    rep = compare(p, g, o, pixels=pix)
+    say({k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+    assert_parity(rep, 0.999, DE_SHADE_FRAC)
+
+
+def test_de_paper_constant_and_eye_inside_box(dqj):
+    import oracle
+    base = workloads.de_128()[0]
+    for p in [base.replace(c=workloads.PAPER_C[1], max_iter=15, width=96, height=72),
+              base.replace(eye=[0.4, 0.9, 1.2], width=80, height=80)]:
+        g = render(dqj, p)
+        o = oracle.render(p)
+        rep = compare(p, g, o)
+        say({k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+        assert_parity(rep, 0.999, DE_SHADE_FRAC)
+
+
+def test_de_modes_not_offered(dqj):
+    import ctypes
+    p = workloads.de_128()[0]
+    sp = dqj.make_params(p.replace(precision=workloads.PREC_SPLIT))
+    fo = dqj.make_frame_out(dqj.alloc_outputs(128, 128))
+    st = dqj.lib().dqj_render(ctypes.byref(sp), ctypes.byref(fo), None)
+    assert st == dqj.E_UNSUPPORTED
+    with pytest.raises(Exception):
+        dqj.render_batch([p, p])
+    with dqj.Server(precision=workloads.PREC_FP32) as srv:
+        st, _ = srv.submit_status(p, dqj.alloc_outputs(128, 128, extras=False))
+        assert st == dqj.E_UNSUPPORTED

@@ -36,6 +36,9 @@ PREC_FP32 = 0
 PREC_SPLIT = 1
 PREC_FP64 = 2
 
+MARCH_FIXED = 0       # S fixed steps over the box segment, then bisection
+MARCH_DE = 1          # distance-estimate steps (the paper's own march)
+
 
 def f32(x: float) -> float:
     """Round one FP64 value to the nearest FP32 value (returned as a Python float)."""
@@ -94,6 +97,10 @@ class Params:
     light_dir: List[float] = dataclasses.field(default_factory=lambda: [1.0, 1.0, 1.0])
     k_ambient: float = 0.1
     k_diffuse: float = 0.9
+    march: int = MARCH_FIXED
+    de_hit_eps: float = 1e-4
+    de_min_step: float = 1e-4
+    de_max_step: float = 0.25
 
     def __post_init__(self):
         self.c = f32v(self.c)
@@ -110,6 +117,9 @@ class Params:
         self.light_dir = f32v(self.light_dir)
         self.k_ambient = f32(self.k_ambient)
         self.k_diffuse = f32(self.k_diffuse)
+        self.de_hit_eps = f32(self.de_hit_eps)
+        self.de_min_step = f32(self.de_min_step)
+        self.de_max_step = f32(self.de_max_step)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -206,6 +216,17 @@ def serve_stream(duration_s: float = 60.0, rate_hz: float = 200.0, seed: int = 5
     return out
 
 
+def de_128(seed: int = 0) -> List[Params]:
+    """plain_128 marched by distance estimates (at most 128 steps)."""
+    return [p.replace(march=MARCH_DE) for p in plain_128(seed)]
+
+
+def de_1024(seeds: Sequence[int] = (0, 1, 2)) -> List[Params]:
+    """plain_1024 marched by distance estimates: the same frames, at most 512 steps,
+    hit below 1e-4, steps clamped to [1e-4, 0.25]."""
+    return [p.replace(march=MARCH_DE) for p in plain_1024(seeds)]
+
+
 def scene_extent(p: Params) -> float:
     """Length of the box diagonal: the scale the depth tolerance is quoted in."""
     return math.sqrt(sum((b - a) ** 2 for a, b in zip(p.box_min, p.box_max)))
@@ -214,6 +235,8 @@ def scene_extent(p: Params) -> float:
 WORKLOADS = {
     "plain_128": plain_128,
     "plain_1024": plain_1024,
+    "de_128": de_128,
+    "de_1024": de_1024,
     "split_1080p": split_1080p,
     "sweep_256": sweep_256,
 }
