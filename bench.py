@@ -40,7 +40,8 @@ TRAFFIC_RECORD = {
     "fetch_kib": 63.27, "fetch_factor": 2.0,
     "write_kib": 37549.26, "write_factor": 1.0,
 }
-TRAFFIC_SOURCES = ["paper_2303_14827_amd/csrc/render_refill.hip", "paper_2303_14827_amd/csrc/dq_device.h",
+TRAFFIC_SOURCES = ["paper_2303_14827_amd/csrc/render_refill.hip", "paper_2303_14827_amd/csrc/persist.h",
+                   "paper_2303_14827_amd/csrc/dq_device.h",
                    "paper_2303_14827_amd/csrc/kparams.h", "paper_2303_14827_amd/csrc/launch.h",
                    "paper_2303_14827_amd/csrc/refill.h", "paper_2303_14827_amd/csrc/runtime_internal.h",
                    "paper_2303_14827_amd/build.py", "include/dqj.h"]
@@ -349,11 +350,11 @@ def bench_sweep(args, dqj, workloads, torch):
 
 
 def bench_de(args, dqj, workloads, torch):
-    """plain_1024's three frames marched by distance estimates (FP32, one-thread-per-pixel
-    kernel, one dqj_render per frame), against the FP64 oracle's count of the updates that
-    march runs (tests/golden/ialg_de_1024.json). Each DE update also carries the derivative
-    norm: 2 more flops than the fixed march's 52."""
-    import numpy as np
+    """plain_1024's three frames marched by distance estimates (FP32, one dqj_render per
+    frame on the default one-thread-per-pixel kernel), against the FP64 oracle's count of
+    the updates that march runs (tests/golden/ialg_de_1024.json). Each DE update also
+    carries the derivative norm: 2 more flops than the fixed march's 52. The persistent
+    lane-refill kernel is timed beside it."""
     ps = workloads.de_1024()
     with open(os.path.join(ROOT, "tests", "golden", "ialg_de_1024.json")) as f:
         ialg = json.load(f)["total_iters"]
@@ -364,21 +365,26 @@ def bench_de(args, dqj, workloads, torch):
     torch.cuda.synchronize()
     counted = sum(int(o["iters"].item()) for o in outs)
     timed = [{k: v for k, v in o.items() if k != "iters"} for o in outs]
-    for _ in range(args.warmup):
-        for p, o in zip(ps, timed):
-            dqj.render(p, out=o, stream=stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        for p, o in zip(ps, timed):
-            dqj.render(p, out=o, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    ev_ms = e0.elapsed_time(e1) / args.steps
+
+    def run(schedule, steps, warmup):
+        for _ in range(warmup):
+            for p, o in zip(ps, timed):
+                dqj.render(p, out=o, stream=stream, schedule=schedule)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            for p, o in zip(ps, timed):
+                dqj.render(p, out=o, stream=stream, schedule=schedule)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
+
+    refill_ms, refill_ev = run(dqj.make_schedule(kernel=dqj.KERNEL_REFILL),
+                               max(1, args.steps // 4), 2)
+    ms, ev_ms = run(None, args.steps, args.warmup)
     flops = FLOPS_PER_UPDATE + 2
     achieved = flops * ialg / (ev_ms * 1e-3) / 1e12
     line = {
@@ -393,7 +399,11 @@ def bench_de(args, dqj, workloads, torch):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
                      "kernel": "render_de_kernel", "kernel_ms_per_step": ev_ms,
-                     "flops_per_update": flops},
+                     "flops_per_update": flops,
+                     "frac_of_measured_fmac_issue": achieved / FP32_FMAC_ISSUE_TFLOPS},
+        "refill_kernel": {"kernel": "render_de_refill_kernel", "ms_per_step": refill_ms,
+                          "kernel_ms_per_step": refill_ev,
+                          "value": ialg / (refill_ms * 1e-3)},
         "ialg_per_step": ialg, "ialg_source": "FP64 oracle, tests/golden/ialg_de_1024.json",
         "gpu_counted_iters_per_step": counted,
         "hits_per_frame": [int(o["mask"].sum().item()) for o in outs],

@@ -27,6 +27,15 @@ hipError_t launch_render_refill_batch(const FrameDesc *table_dev, const LaunchHe
                                       bool any_count, uint32_t *counter, const Sched &s, int cus,
                                       hipStream_t stream);
 
+// Distance-estimate march on the same persistent design: one frame, or n frames of one
+// norm from a device table (all_axis: every frame uses the identity slice).
+hipError_t launch_render_de_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
+                                   hipStream_t stream);
+hipError_t launch_render_de_refill_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
+                                         int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                         bool any_count, uint32_t *counter, const Sched &s, int cus,
+                                         hipStream_t stream);
+
 // Fill the tile geometry of a frame descriptor (tile_begin must be set by the caller).
 inline void set_tiles(FrameDesc &f, int tw, int th) {
   f.tiles_x = (uint32_t)((f.P.W + tw - 1) / tw);

@@ -1,11 +1,17 @@
 // render_de.hip -- distance-estimate ray march (section "Ray-Marching", Eq. distfract2).
 //
-// One thread per pixel. From the box entry the ray is stepped by the distance estimate
+// From the box entry the ray is stepped by the distance estimate
 // 0.5 |z_m| ln|z_m| / |z'_m| of the current point, clamped to [de_min_step, de_max_step],
 // until the estimate falls below de_hit_eps (hit there), a step lands inside the set
 // (the step is bisected B times), the ray leaves the box, or S steps were taken (miss).
 // The derivative norm follows |z'_{n+1}| = 2 |z_n| |z'_n| from |z'_0| = 1 (Eq. distfract;
 // norms are the escape norm). Normal and shade are those of the fixed-step path.
+//
+// Two kernels: render_de_refill_kernel, the production form, is the persistent
+// lane-refill design of render_refill.hip (one update per trip on every lane; a march
+// point that escapes computes its estimate and starts the next point at once; hits,
+// misses, bisection and normal points take the slow path; idle lanes take new rays of
+// the wave's tile), and render_de_kernel, one thread per pixel, the yardstick.
 //
 // FP32 range: |z'_n|^2 grows like (4 R^2)^n, beyond FP32 for n >= 22 at R = 4, so the
 // kernel carries D_n = |z'_n|^2 / (4 R^2)^n, which obeys D_{n+1} = D_n |z_n|^2 / R^2 and
@@ -15,6 +21,9 @@
 // then +inf and the step is clamped to de_max_step, as a huge estimate would be.
 #include "dq_device.h"
 #include "launch.h"
+#include "persist.h"
+#include "refill.h"
+#include <cstring>
 
 namespace dqj {
 
@@ -149,6 +158,362 @@ hipError_t launch_render_de(const KParams &P, const KOut &out, hipStream_t s) {
   else
     hipLaunchKernelGGL(render_de_kernel<1>, grid, dim3(256), 0, s, P, out);
   return hipGetLastError();
+}
+
+}  // namespace dqj
+
+// ---------------------------------------------------------------------------
+// Persistent lane-refill form.
+// ---------------------------------------------------------------------------
+namespace dqj {
+
+using namespace persist;
+
+namespace {
+
+enum { DE_IDLE = 0, DE_MARCH = 1, DE_BISECT = 2, DE_NORMAL = 3 };
+
+template <bool AXIS>
+__device__ __forceinline__ void de_start(const KParams &P, float x, float y, float w, DQ<float> &z,
+                                         float &s) {
+  if (AXIS) {
+    z = DQ<float>{x, y, w, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    s = fmaf(w, w, y * y);
+  } else {
+    z = slice_map<float>(P, x, y, w);
+    s = vec_s(z);
+  }
+}
+
+template <int NORM>
+__device__ __forceinline__ float norm2_of(const DQ<float> &z, float s) {
+  float n2 = fmaf(z.a0, z.a0, s);
+  if (NORM == 0) n2 = fmaf(z.b3, z.b3, fmaf(z.b2, z.b2, fmaf(z.b1, z.b1, fmaf(z.b0, z.b0, n2))));
+  return n2;
+}
+
+}  // namespace
+
+template <int NORM, bool AXIS, bool BATCH, bool COUNT>
+__global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single,
+                                                                const FrameDesc *__restrict__ table,
+                                                                const LaunchHeader *__restrict__ hdr,
+                                                                int nframes, uint32_t total_tiles,
+                                                                uint32_t *__restrict__ counter,
+                                                                int TW, int TH) {
+  const int lane = lane_id();
+  const int tile_rays = TW * TH;
+  if constexpr (BATCH) {
+    if (hdr) {
+      nframes = (int)uniform(((ConstHeader)hdr)->nframes);
+      total_tiles = uniform(((ConstHeader)hdr)->total_tiles);
+    }
+  }
+  const float kNaN = __builtin_nanf("");
+  const ConstFrame ctable = (ConstFrame)table;
+  typename FramePtr<BATCH>::type F;
+  if constexpr (BATCH)
+    F = nullptr;
+  else
+    F = &single;
+  int frame = -1;
+  uint32_t tile_local = 0;
+  int next_r = 0;
+  bool have_tile = false, pending = false, exhausted = false;
+  uint32_t pend_tile = 0;
+  float c[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) c[q] = 0.0f;
+  float R2 = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  float inv_r2 = 0.0f, l4r2 = 0.0f, eps = 0.0f, smin = 0.0f, smax = 0.0f;
+  int N = 1, S = 1;
+  // trip counter and deadlines as in render_refill_kernel
+  uint32_t trip = 0;
+  const uint32_t kIdleAhead = 0x7FFFFFFFu;
+
+  int phase = DE_IDLE;
+  DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+  float s = kNaN;
+  float D = 1.0f;          // |z'_n|^2 / (4 R^2)^n of the current march point
+  float n2prev = 0.0f;     // |z_n|^2 of the current point (the next derivative step needs it)
+  uint32_t dl = kIdleAhead;
+  int pix = 0;
+  float dx = 0, dy = 0, dz = 0, t0 = 0, t1 = 0, t = 0, tprev = 0;
+  int k = 0, b = 0, sidx = 0, kstar = -1;
+  float lo = 0, hi = 0, thit = 0, gx = 0, gy = 0, gz = 0;
+  uint32_t it_lane = 0;
+
+  for (;;) {
+    ++trip;
+    // ---- one update on every lane, the derivative norm carried along
+    D = D * (n2prev * inv_r2);
+    const float n2 = dq_update<NORM>(z, s, c);
+    n2prev = n2;
+    const bool esc = n2 > R2;
+    const bool expired = (int)(trip - dl) >= 0;
+
+    // ---- an escaped march point: its distance estimate and the next step
+    bool fast = false;
+    float de = 0.0f;
+    if (esc && phase == DE_MARCH) {
+      const int m = N - (int)(dl - trip);
+      const float l2n = __builtin_amdgcn_logf(n2);
+      const float q = 0.5f * (l2n - __builtin_amdgcn_logf(D) - (float)m * l4r2);
+      de = 0.25f * 0.69314718f * l2n * __builtin_amdgcn_exp2f(q);
+      const float tn = t + fminf(fmaxf(de, smin), smax);
+      fast = de >= eps && tn <= t1 && k + 1 < S;
+      if (fast) {
+        if (COUNT) it_lane += (uint32_t)m;
+        tprev = t;
+        t = tn;
+        ++k;
+        de_start<AXIS>(F->P, fmaf(t, dx, ex), fmaf(t, dy, ey), fmaf(t, dz, ez), z, s);
+        n2prev = norm2_of<NORM>(z, s);
+        D = 1.0f;
+        dl = trip + (uint32_t)N;
+      }
+    }
+
+    // ---- everything else that retires: march end (hit, miss), bisection, normal
+    if ((esc || expired) && !fast) {
+      const KParams &P = F->P;
+      float n2c = n2;
+      asm volatile("" : "+v"(n2c));
+      const bool inside = !(n2c > R2);
+      const int m = N - (int)(dl - trip);
+      if (COUNT) it_lane += (uint32_t)m;
+      bool next_normal = false, restart = false;
+      float tr = 0.0f;
+      if (phase == DE_MARCH) {
+        if (inside) {              // the step landed inside: bisect it (or hit at t0)
+          kstar = k;
+          if (k == 0) {
+            thit = t0;
+            next_normal = true;
+          } else {
+            lo = tprev;
+            hi = t;
+            if (P.B == 0) {
+              thit = 0.5f * (lo + hi);
+              next_normal = true;
+            } else {
+              b = 0;
+              phase = DE_BISECT;
+              tr = 0.5f * (lo + hi);
+              restart = true;
+            }
+          }
+        } else if (de < eps) {     // the estimate fell below the threshold: hit here
+          kstar = k;
+          thit = t;
+          next_normal = true;
+        } else {                   // left the box or ran out of steps: miss
+          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+          phase = DE_IDLE;
+        }
+      } else if (phase == DE_BISECT) {
+        const float tm = 0.5f * (lo + hi);
+        if (inside)
+          hi = tm;
+        else
+          lo = tm;
+        ++b;
+        if (b >= P.B) {
+          thit = 0.5f * (lo + hi);
+          next_normal = true;
+        } else {
+          tr = 0.5f * (lo + hi);
+          restart = true;
+        }
+      } else {   // DE_NORMAL: stencil point sidx just retired
+        const float G = potential(n2, m);
+        const float sg = (sidx & 1) ? -G : G;
+        const int axis = sidx >> 1;
+        if (axis == 0)
+          gx += sg;
+        else if (axis == 1)
+          gy += sg;
+        else
+          gz += sg;
+        ++sidx;
+        if (sidx == 6) {
+          const float g[3] = {gx, gy, gz};
+          const float d[3] = {dx, dy, dz};
+          PixelOut r;
+          finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+          write_pixel(F->out, pix, r);
+          phase = DE_IDLE;
+        }
+      }
+      if (next_normal) {
+        phase = DE_NORMAL;
+        sidx = 0;
+        gx = gy = gz = 0.0f;
+      }
+      float px = 0, py = 0, pz = 0;
+      if (restart) {
+        px = fmaf(tr, dx, ex);
+        py = fmaf(tr, dy, ey);
+        pz = fmaf(tr, dz, ez);
+      } else if (phase == DE_NORMAL) {
+        const int axis = sidx >> 1;
+        const float hs = (sidx & 1) ? -P.h : P.h;
+        px = fmaf(thit, dx, ex) + (axis == 0 ? hs : 0.0f);
+        py = fmaf(thit, dy, ey) + (axis == 1 ? hs : 0.0f);
+        pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
+      }
+      if (phase != DE_IDLE) {
+        de_start<AXIS>(P, px, py, pz, z, s);
+        dl = trip + (uint32_t)N;
+      } else {
+        z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+        s = kNaN;
+        dl = trip + kIdleAhead;
+      }
+    }
+
+    // ---- hand new rays to idle lanes
+    uint64_t idle = __builtin_amdgcn_ballot_w64(phase == DE_IDLE);
+    while (idle) {
+      if (!have_tile) {
+        if (exhausted) break;
+        if (!pending) {
+          uint32_t tt = 0;
+          if (lane == 0) tt = atomicAdd(counter, 1u);
+          tt = uniform(tt);
+          if (tt >= total_tiles) {
+            exhausted = true;
+            break;
+          }
+          pend_tile = tt;
+          pending = true;
+        }
+        const int f = BATCH ? find_frame(ctable, nframes, pend_tile) : 0;
+        if (f != frame) {
+          if (idle != ~0ull) break;  // finish this frame's rays first
+          if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+          it_lane = 0;
+          frame = f;
+          if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) c[q] = uniform_f(F->P.c[q]);
+          R2 = uniform_f(F->P.R2);
+          N = (int)uniform((uint32_t)F->P.N);
+          S = (int)uniform((uint32_t)F->P.S);
+          ex = uniform_f(F->P.eye[0]);
+          ey = uniform_f(F->P.eye[1]);
+          ez = uniform_f(F->P.eye[2]);
+          inv_r2 = uniform_f(F->P.de_inv_r2);
+          l4r2 = uniform_f(F->P.de_log2_4r2);
+          eps = uniform_f(F->P.de_eps);
+          smin = uniform_f(F->P.de_min_step);
+          smax = uniform_f(F->P.de_max_step);
+        }
+        tile_local = pend_tile - F->tile_begin + F->tile_offset;
+        pending = false;
+        have_tile = true;
+        next_r = 0;
+      }
+      const int rank = rank_in(idle);
+      const int avail = tile_rays - next_r;
+      if (phase == DE_IDLE && rank < avail) {
+        const KParams &P = F->P;
+        const int r = next_r + rank;
+        const int i = (int)(tile_local % F->tiles_x) * TW + r % TW;
+        const int j = (int)(tile_local / F->tiles_x) * TH + r / TW;
+        if (i < P.W && j < P.H) {
+          pix = j * P.W + i;
+          float d[3];
+          pixel_dir(P, i, j, d);
+          float ta, tb;
+          if (clip_box(P, d, ta, tb)) {
+            dx = d[0];
+            dy = d[1];
+            dz = d[2];
+            t0 = ta;
+            t1 = tb;
+            t = ta;
+            tprev = ta;
+            k = 0;
+            kstar = -1;
+            phase = DE_MARCH;
+            de_start<AXIS>(P, fmaf(t, dx, ex), fmaf(t, dy, ey), fmaf(t, dz, ez), z, s);
+            n2prev = norm2_of<NORM>(z, s);
+            D = 1.0f;
+            dl = trip + (uint32_t)N;
+          } else {
+            write_pixel(F->out, pix, miss_pixel(0));
+          }
+        }
+      }
+      const int cnt = __popcll(idle);
+      next_r += cnt < avail ? cnt : avail;
+      if (next_r >= tile_rays) have_tile = false;
+      idle = __builtin_amdgcn_ballot_w64(phase == DE_IDLE);
+    }
+
+    if (exhausted && !__builtin_amdgcn_ballot_w64(phase != DE_IDLE)) break;
+  }
+  if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+}
+
+__global__ void de_reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
+
+template <bool BATCH, bool COUNT>
+static void launch_de_variant(const FrameDesc &single, const FrameDesc *table,
+                              const LaunchHeader *hdr, int nframes, uint32_t total_tiles,
+                              int norm, bool axis, uint32_t *counter, const Sched &s, int blocks,
+                              int threads, hipStream_t stream) {
+#define DQJ_DE_LAUNCH(NM, AX)                                                                   \
+  hipLaunchKernelGGL((render_de_refill_kernel<NM, AX, BATCH, COUNT>), dim3(blocks),              \
+                     dim3(threads), 0, stream, single, table, hdr, nframes, total_tiles, counter, \
+                     s.tile_w, s.tile_h)
+  if (norm == 0) {
+    if (axis)
+      DQJ_DE_LAUNCH(0, true);
+    else
+      DQJ_DE_LAUNCH(0, false);
+  } else {
+    if (axis)
+      DQJ_DE_LAUNCH(1, true);
+    else
+      DQJ_DE_LAUNCH(1, false);
+  }
+#undef DQJ_DE_LAUNCH
+}
+
+template <bool BATCH>
+static hipError_t launch_de_impl(const FrameDesc &single, const FrameDesc *table,
+                                 const LaunchHeader *hdr, int nframes, uint32_t total_tiles,
+                                 int norm, bool axis, bool count, uint32_t *counter,
+                                 const Sched &s, int cus, hipStream_t stream) {
+  hipLaunchKernelGGL(de_reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+  const int threads = 64 * s.waves_per_block;
+  const int blocks = cus * s.blocks_per_cu;
+  if (count)
+    launch_de_variant<BATCH, true>(single, table, hdr, nframes, total_tiles, norm, axis, counter, s,
+                                   blocks, threads, stream);
+  else
+    launch_de_variant<BATCH, false>(single, table, hdr, nframes, total_tiles, norm, axis, counter, s,
+                                    blocks, threads, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_de_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
+                                   hipStream_t stream) {
+  return launch_de_impl<false>(frame, nullptr, nullptr, 1, frame.ntiles, frame.P.norm,
+                               frame.P.axis_slice != 0, frame.out.iters != nullptr, counter, s, cus,
+                               stream);
+}
+
+hipError_t launch_render_de_refill_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
+                                         int nframes, uint32_t total_tiles, int norm, bool all_axis,
+                                         bool any_count, uint32_t *counter, const Sched &s, int cus,
+                                         hipStream_t stream) {
+  FrameDesc dummy;
+  memset(&dummy, 0, sizeof dummy);
+  return launch_de_impl<true>(dummy, table_dev, hdr_dev, nframes, total_tiles, norm, all_axis,
+                              any_count, counter, s, cus, stream);
 }
 
 }  // namespace dqj

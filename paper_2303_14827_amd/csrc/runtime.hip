@@ -423,7 +423,23 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
   if (params->march == DQJ_MARCH_DE) {
     if (params->precision != DQJ_PREC_FP32)
       return fail(DQJ_E_UNSUPPORTED, "the distance-estimate march runs in FP32 only");
-    e = launch_render_de(kp, ko, stream);
+    // The one-thread-per-pixel kernel is the default here: DE march points escape after
+    // a few updates, so the refill kernel's per-point estimate and restart run on nearly
+    // every trip; the persistent form is taken only when asked for.
+    const Sched sc = resolve_schedule(sched, cus);
+    if (!sched || sched->kernel != DQJ_KERNEL_REFILL) {
+      e = launch_render_de(kp, ko, stream);
+    } else {
+      FrameDesc f;
+      memset(&f, 0, sizeof f);
+      f.P = kp;
+      f.out = ko;
+      f.tile_begin = 0;
+      set_tiles(f, sc.tile_w, sc.tile_h);
+      uint32_t *counter = nullptr;
+      e = stream_counter(stream, &counter);
+      if (e == hipSuccess) e = launch_render_de_refill(f, counter, sc, cus, stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return DQJ_OK;
   }

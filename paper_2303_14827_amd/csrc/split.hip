@@ -22,10 +22,13 @@
 
 #include "dq_device.h"
 #include "launch.h"
+#include "persist.h"
 #include "refill.h"
 #include "split.h"
 
 namespace dqj {
+
+using namespace persist;
 
 namespace {
 
@@ -86,48 +89,6 @@ __device__ __forceinline__ h2 pk_update(DQH &z, h2 &s, const h2 *c) {
   h2 n2 = hfma(z.a0, z.a0, s);
   if (NORM == 0) n2 = hfma(z.b3, z.b3, hfma(z.b2, z.b2, hfma(z.b1, z.b1, hfma(z.b0, z.b0, n2))));
   return n2;
-}
-
-__device__ __forceinline__ int rank_in(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-__device__ __forceinline__ int lane_id() {
-  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-__device__ __forceinline__ uint32_t uniform(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-__device__ __forceinline__ float uniform_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-
-#if defined(__HIP_DEVICE_COMPILE__)
-typedef const __attribute__((address_space(4))) FrameDesc *ConstFrame;
-typedef const __attribute__((address_space(4))) LaunchHeader *ConstHeader;
-#else
-typedef const FrameDesc *ConstFrame;
-typedef const LaunchHeader *ConstHeader;
-#endif
-
-template <bool BATCH>
-struct FramePtr {
-  typedef const FrameDesc *type;
-};
-template <>
-struct FramePtr<true> {
-  typedef ConstFrame type;
-};
-
-__device__ __forceinline__ int find_frame(ConstFrame table, int nframes, uint32_t tile) {
-  int lo = 0, hi = nframes - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (table[mid].tile_begin <= tile)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
 }
 
 // Pixel direction in FP64 (for the FP64 pass).

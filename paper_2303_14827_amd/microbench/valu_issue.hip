@@ -5,7 +5,8 @@
 // (4 blocks of 256 threads per CU). Every wave records the 100 MHz constant clock at the
 // start and end of its loop; the span over all waves gives the time per instruction per
 // SIMD. A second set runs one wave per SIMD over a single dependent chain to give latency.
-// Registers only: the one store per wave goes to its own slot of `out`.
+// Registers only: the one store per wave goes to its own slot of `out`. The control-flow
+// forms restore exec inside their own block and branch only to the next instruction.
 //
 // Build and run:  hipcc -O3 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops \
 //                   -o valu_issue valu_issue.hip && ./valu_issue
@@ -39,6 +40,18 @@
               "v_min_f16_sdwa %13, %13, %10 dst_sel:WORD_0 dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:WORD_1\n\t"
 #define MIX4 "v_fma_mixlo_f16 %10, %0, %8, %9\n\tv_fma_mixhi_f16 %10, %1, %8, %9\n\t" \
              "v_fma_mixlo_f16 %11, %2, %8, %9\n\tv_fma_mixhi_f16 %11, %3, %8, %9\n\t"
+#define LOG4 "v_log_f32 %10, %10\n\tv_log_f32 %11, %11\n\tv_log_f32 %12, %12\n\tv_log_f32 %13, %13\n\t"
+#define EXP4 "v_exp_f32 %10, %10\n\tv_exp_f32 %11, %11\n\tv_exp_f32 %12, %12\n\tv_exp_f32 %13, %13\n\t"
+#define RSQ4 "v_rsq_f32 %10, %10\n\tv_rsq_f32 %11, %11\n\tv_rsq_f32 %12, %12\n\tv_rsq_f32 %13, %13\n\t"
+// a uniform conditional branch (never taken) and an exec-masked region around nothing:
+// the cost of the control flow the state machines compile to
+#define BR1 "s_cmp_eq_u32 s98, s99\n\ts_cbranch_scc1 1f\n1:\n\t"
+// (EXEC0: the compare is false on every lane, so the region is skipped by a taken branch;
+// EXEC1: true on every lane, branch not taken)
+#define EXEC0 "v_cmp_gt_f32 vcc, %10, %11\n\ts_and_saveexec_b64 s[98:99], vcc\n\t" \
+              "s_cbranch_execz 1f\n1:\n\ts_or_b64 exec, exec, s[98:99]\n\t"
+#define EXEC1 "v_cmp_gt_f32 vcc, %8, %9\n\ts_and_saveexec_b64 s[98:99], vcc\n\t" \
+              "s_cbranch_execz 1f\n1:\n\ts_or_b64 exec, exec, s[98:99]\n\t"
 #define MOV64_4 "v_mov_b64 v[100:101], s[98:99]\n\tv_mov_b64 v[102:103], s[98:99]\n\t" \
                 "v_mov_b64 v[100:101], s[98:99]\n\tv_mov_b64 v[102:103], s[98:99]\n\t"
 
@@ -52,7 +65,7 @@
       asm volatile(BODY : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6),  \
                    "+v"(a7), "+v"(x), "+v"(y), "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3)            \
                    :                                                                             \
-                   : "vcc", "s98", "s99", "v100", "v101", "v102", "v103");                       \
+                   : "vcc", "scc", "s98", "s99", "v100", "v101", "v102", "v103");                     \
     }                                                                                            \
     asm volatile("s_memrealtime %0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r1) : "v"(a0), "v"(a7), "v"(b0)); \
     const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64;                                  \
@@ -79,6 +92,12 @@ KERNEL(k_fmac_cnd, R8(FMAC_VV) CND_V CND_V)
 KERNEL(k_fmac_sdwa, R8(FMAC_VV) SDWA4 SDWA4)
 KERNEL(k_fmac_mix, R8(FMAC_VV) MIX4 MIX4)
 KERNEL(k_fmac_mov64, R8(FMAC_VV) MOV64_4 MOV64_4)
+KERNEL(k_fmac_log, R8(FMAC_VV) LOG4 LOG4)
+KERNEL(k_fmac_exp, R8(FMAC_VV) EXP4 EXP4)
+KERNEL(k_fmac_rsq, R8(FMAC_VV) RSQ4 RSQ4)
+KERNEL(k_fmac_br, R8(FMAC_VV) BR1 BR1 BR1 BR1 BR1 BR1 BR1 BR1)
+KERNEL(k_fmac_exec0, R8(FMAC_VV) EXEC0 EXEC0 EXEC0 EXEC0 EXEC0 EXEC0 EXEC0 EXEC0)
+KERNEL(k_fmac_exec1, R8(FMAC_VV) EXEC1 EXEC1 EXEC1 EXEC1 EXEC1 EXEC1 EXEC1 EXEC1)
 
 // One dependent chain per wave, one wave per SIMD: latency of dependent FP32 FMA and packed FP16 FMA.
 #define CHAIN_F32 "v_fmac_f32 %0, %8, %9\n\t"
@@ -131,6 +150,12 @@ int main() {
       {"v_min_f16_sdwa", k_fmac_sdwa, 8, true},
       {"v_fma_mix{lo,hi}_f16", k_fmac_mix, 8, true},
       {"v_mov_b64 (from SGPR pair)", k_fmac_mov64, 8, true},
+      {"v_log_f32", k_fmac_log, 8, true},
+      {"v_exp_f32", k_fmac_exp, 8, true},
+      {"v_rsq_f32", k_fmac_rsq, 8, true},
+      {"s_cmp + s_cbranch_scc1 (not taken)", k_fmac_br, 8, true},
+      {"masked region, skipped (branch taken)", k_fmac_exec0, 8, true},
+      {"masked region, entered (not taken)", k_fmac_exec1, 8, true},
   };
   // 4 waves per SIMD: 4 blocks of 256 threads per CU
   const double base = span_ns(k_fmac_vv, 4, 256, cus, d) / (4.0 * ITERS * 8);

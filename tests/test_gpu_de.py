@@ -1,5 +1,7 @@
 """GPU distance-estimate march (FP32) against the FP64 oracle's DE march, and the
-c = 0 closed form: every hit bisected onto the ball of radius R^(2^-N).
+c = 0 closed form: every hit bisected onto the ball of radius R^(2^-N). Both kernels
+run: the one-thread-per-pixel kernel (the default for this march) and the persistent
+lane-refill kernel (KERNEL_REFILL).
 
 Mask and depth meet the plain path's bar. Shading is held to 99% of agreeing hits
 within 1/255 (DE_SHADE_FRAC): a DE hit is where a chaotic estimate first drops below the
@@ -31,20 +33,29 @@ def dqj():
     return m
 
 
-def render(dqj, p):
+KERNELS = ["refill", "direct"]
+
+
+def sched(dqj, kernel):
+    k = dqj.KERNEL_REFILL if kernel == "refill" else dqj.KERNEL_DIRECT
+    return dqj.make_schedule(kernel=k)
+
+
+def render(dqj, p, kernel="direct"):
     import torch
-    o = dqj.render(p)
+    o = dqj.render(p, schedule=sched(dqj, kernel))
     torch.cuda.synchronize()
     return to_numpy(o)
 
 
-def test_de_c0_closed_form(dqj):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_de_c0_closed_form(dqj, kernel):
     from test_oracle_render import analytic_ball
     import oracle
     N, B = 12, 8
     p = workloads.Params(c=[0.0] * 8, width=48, height=48, max_iter=N, march_steps=400,
                          bisect_steps=B, march=workloads.MARCH_DE)
-    g = render(dqj, p)
+    g = render(dqj, p, kernel)
     rho = 4.0 ** (2.0 ** -N)
     n = 0
     for j in range(p.height):
@@ -63,11 +74,12 @@ def test_de_c0_closed_form(dqj):
     assert n > 400
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("norm", [workloads.NORM_EUCLID8, workloads.NORM_REALPART])
-def test_de_128_full_frame(dqj, norm):
+def test_de_128_full_frame(dqj, norm, kernel):
     import oracle
     p = workloads.de_128()[0].replace(norm=norm)
-    g = render(dqj, p)
+    g = render(dqj, p, kernel)
     o = oracle.render(p)
     rep = compare(p, g, o)
     say(norm, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
@@ -75,10 +87,12 @@ def test_de_128_full_frame(dqj, norm):
     assert_parity(rep, 0.999, DE_SHADE_FRAC)
 
 
-def test_de_1024_sampled(dqj):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_de_1024_sampled(dqj, kernel):
+    """The 1024x1024 DE frame in the benchmark's launch configurations."""
     import oracle
     p = workloads.de_1024()[2]
-    g = render(dqj, p)
+    g = render(dqj, p, kernel)
     pix = sample_pixels(p, 2500, 3)
     hits = np.nonzero(g["mask"].reshape(-1))[0]
     pix = np.union1d(pix, np.random.default_rng(4).choice(hits, 1500, replace=False))
@@ -88,16 +102,52 @@ def test_de_1024_sampled(dqj):
     assert_parity(rep, 0.999, DE_SHADE_FRAC)
 
 
-def test_de_paper_constant_and_eye_inside_box(dqj):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_de_paper_constant_and_eye_inside_box(dqj, kernel):
     import oracle
     base = workloads.de_128()[0]
     for p in [base.replace(c=workloads.PAPER_C[1], max_iter=15, width=96, height=72),
               base.replace(eye=[0.4, 0.9, 1.2], width=80, height=80)]:
-        g = render(dqj, p)
+        g = render(dqj, p, kernel)
         o = oracle.render(p)
         rep = compare(p, g, o)
         say({k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
         assert_parity(rep, 0.999, DE_SHADE_FRAC)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("case", ["ragged_131x97", "tiny_1x1", "S1", "N1", "B0", "dual_slice",
+                                  "steps_clamped_small"])
+def test_de_edge_cases(dqj, case, kernel):
+    """Degenerate sizes and parameters of the DE march on both kernels: a ragged
+    frame over several tiles, one pixel, one march step, one update (every estimate is
+    that of z_1), no bisection, a slice through the dual part, and a step range so
+    narrow that rays run out of steps inside the box."""
+    import oracle
+    base = workloads.de_128()[0]
+    if case == "ragged_131x97":
+        p = base.replace(width=131, height=97)
+    elif case == "tiny_1x1":
+        p = base.replace(width=1, height=1, eye=[0.0, 0.0, 3.0], c=[-0.2, 0.1, 0, 0, 0, 0, 0, 0])
+    elif case == "S1":
+        p = base.replace(march_steps=1, c=[-0.2, 0.1, 0, 0, 0.1, 0, 0, 0])
+    elif case == "N1":
+        p = base.replace(max_iter=1)
+    elif case == "B0":
+        p = base.replace(bisect_steps=0)
+    elif case == "dual_slice":
+        axes = [[1.0, 0, 0, 0, 0, 0, 0, 0], [0, 1.0, 0, 0, 0, 0, 0, 0], [0, 0, 0, 0, 1.0, 0, 0, 0]]
+        p = base.replace(slice_axes=axes, slice_origin=[0, 0, 0.1, 0, 0, 0, 0, 0],
+                         c=[-0.39054, -0.58679, 0, 0, 0.0, 0.5632, 0, 0.05], max_iter=15)
+    else:
+        p = base.replace(de_min_step=1e-3, de_max_step=2e-3, march_steps=200)
+    p.__post_init__()
+    say(case, kernel)
+    g = render(dqj, p, kernel)
+    o = oracle.render(p)
+    rep = compare(p, g, o)
+    say({k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+    assert_parity(rep, 0.999, DE_SHADE_FRAC)
 
 
 def test_de_modes_not_offered(dqj):
