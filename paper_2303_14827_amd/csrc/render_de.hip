@@ -29,33 +29,70 @@ namespace dqj {
 
 namespace {
 
-// Classify with the scaled derivative: returns the escape index m (0 when inside) and,
-// for an escaping point, the distance estimate in *de.
-template <int NORM>
-__device__ __forceinline__ int classify_de(const KParams &P, DQ<float> z, float *de, float *n2out) {
-  float s = vec_s(z);
-  float n2prev = fmaf(z.a0, z.a0, s);
-  if (NORM == 0) n2prev = fmaf(z.b3, z.b3, fmaf(z.b2, z.b2, fmaf(z.b1, z.b1, fmaf(z.b0, z.b0, n2prev))));
-  float D = 1.0f;
-  for (int n = 1; n <= P.N; ++n) {
-    D = D * (n2prev * P.de_inv_r2);
-    const float n2 = dq_update<NORM>(z, s, P.c);
-    if (n2 > P.R2) {
-      const float l2n = __builtin_amdgcn_logf(n2);     // log2 |z_m|^2
-      const float q = 0.5f * (l2n - __builtin_amdgcn_logf(D) - (float)n * P.de_log2_4r2);
-      // 0.5 |z| ln|z| / |z'| = 0.5 * 2^q * (ln 2 / 2) * log2 |z|^2
-      *de = 0.25f * 0.69314718f * l2n * __builtin_amdgcn_exp2f(q);
-      *n2out = n2;
-      return n;
-    }
-    n2prev = n2;
+// zeta_0 of a world point and |a_v|^2 of it (identity slice: (x, y, w, 0 | 0)).
+template <bool AXIS>
+__device__ __forceinline__ void de_start(const KParams &P, float x, float y, float w, DQ<float> &z,
+                                         float &s) {
+  if (AXIS) {
+    z = DQ<float>{x, y, w, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    s = fmaf(w, w, y * y);
+  } else {
+    z = slice_map<float>(P, x, y, w);
+    s = vec_s(z);
   }
-  *n2out = n2prev;
-  return 0;
 }
 
 template <int NORM>
-__device__ void render_pixel_de(const KParams &P, int i, int j, PixelOut &r,
+__device__ __forceinline__ float norm2_of(const DQ<float> &z, float s) {
+  float n2 = fmaf(z.a0, z.a0, s);
+  if (NORM == 0) n2 = fmaf(z.b3, z.b3, fmaf(z.b2, z.b2, fmaf(z.b1, z.b1, fmaf(z.b0, z.b0, n2))));
+  return n2;
+}
+
+// One update with c in vector registers (in place for the 8-square norm).
+template <int NORM>
+__device__ __forceinline__ float de_update(DQ<float> &z, float &s, const float *cv) {
+  if constexpr (NORM == 0)
+    return dq_update_inplace_v(z, s, cv);
+  else
+    return dq_update<NORM>(z, s, cv);
+}
+
+// Estimate 0.5 |z_m| ln|z_m| / |z'_m| from n2 = |z_m|^2 and D = D_m:
+// 0.5 |z| ln|z| / |z'| = 0.5 * 2^q * (ln 2 / 2) * log2 |z|^2.
+__device__ __forceinline__ float de_estimate(float n2, float D, int m, float log2_4r2) {
+  const float l2n = __builtin_amdgcn_logf(n2);
+  const float q = 0.5f * (l2n - __builtin_amdgcn_logf(D) - (float)m * log2_4r2);
+  return 0.25f * 0.69314718f * l2n * __builtin_amdgcn_exp2f(q);
+}
+
+// Escape index m of zeta_0 = z (0 when it stays inside for N updates) with |z_m|^2 in
+// *n2out (|z_N|^2 when inside) and, when DE, the distance estimate of an escaping point
+// in *de. The estimate is formed once, after the loop.
+template <int NORM, bool DE>
+__device__ __forceinline__ int classify_de(const KParams &P, const float *cv, DQ<float> z, float s,
+                                           float *de, float *n2out) {
+  float n2 = norm2_of<NORM>(z, s);
+  float D = 1.0f;
+  int n = 0;
+  bool esc = false;
+  while (n < P.N) {
+    ++n;
+    if (DE) D = D * (n2 * P.de_inv_r2);
+    n2 = de_update<NORM>(z, s, cv);
+    if (n2 > P.R2) {
+      esc = true;
+      break;
+    }
+  }
+  *n2out = n2;
+  if (!esc) return 0;
+  if (DE) *de = de_estimate(n2, D, n, P.de_log2_4r2);
+  return n;
+}
+
+template <int NORM, bool AXIS>
+__device__ void render_pixel_de(const KParams &P, const float *cv, int i, int j, PixelOut &r,
                                 unsigned long long &iters) {
   float d[3];
   pixel_dir(P, i, j, d);
@@ -69,10 +106,11 @@ __device__ void render_pixel_de(const KParams &P, int i, int j, PixelOut &r,
   bool bisect = false;
   float t = t0, tprev = t0;
   for (int k = 0; k < P.S; ++k) {
-    DQ<float> z = slice_map<float>(P, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]),
-                                   fmaf(t, d[2], P.eye[2]));
+    DQ<float> z;
+    float s;
+    de_start<AXIS>(P, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]), fmaf(t, d[2], P.eye[2]), z, s);
     float de = 0.0f, n2;
-    const int m = classify_de<NORM>(P, z, &de, &n2);
+    const int m = classify_de<NORM, true>(P, cv, z, s, &de, &n2);
     iters += m ? m : P.N;
     if (m == 0) {   // inside: the hit is t0 on the first point, else bisect the last step
       kstar = k;
@@ -97,14 +135,14 @@ __device__ void render_pixel_de(const KParams &P, int i, int j, PixelOut &r,
     r = miss_pixel(DQJ_FLAG_BOX);
     return;
   }
-  const float *c = P.c;
   if (bisect) {
     for (int b = 0; b < P.B; ++b) {
       const float tm = 0.5f * (lo + hi);
-      DQ<float> z = slice_map<float>(P, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]),
-                                     fmaf(tm, d[2], P.eye[2]));
-      float n2;
-      const int m = dq_classify<NORM>(z, c, P.N, P.R2, &n2);
+      DQ<float> z;
+      float s, n2, unused;
+      de_start<AXIS>(P, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]), fmaf(tm, d[2], P.eye[2]),
+                     z, s);
+      const int m = classify_de<NORM, false>(P, cv, z, s, &unused, &n2);
       iters += m ? m : P.N;
       if (m == 0)
         hi = tm;
@@ -123,9 +161,10 @@ __device__ void render_pixel_de(const KParams &P, int i, int j, PixelOut &r,
     for (int sgn = 0; sgn < 2; ++sgn) {
       float x[3] = {ph[0], ph[1], ph[2]};
       x[a] = sgn == 0 ? ph[a] + P.h : ph[a] - P.h;
-      DQ<float> z = slice_map<float>(P, x[0], x[1], x[2]);
-      float n2;
-      int m = dq_classify<NORM>(z, c, P.N, P.R2, &n2);
+      DQ<float> z;
+      float s, n2, unused;
+      de_start<AXIS>(P, x[0], x[1], x[2], z, s);
+      int m = classify_de<NORM, false>(P, cv, z, s, &unused, &n2);
       m = m ? m : P.N;
       iters += m;
       const float G = potential(n2, m);
@@ -136,14 +175,17 @@ __device__ void render_pixel_de(const KParams &P, int i, int j, PixelOut &r,
   finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
 }
 
-template <int NORM>
+template <int NORM, bool AXIS>
 __global__ __launch_bounds__(256) void render_de_kernel(KParams P, KOut out) {
   const int i = blockIdx.x * 16 + (threadIdx.x & 15);
   const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+  float cv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(P.c[q]);
   unsigned long long iters = 0;
   if (i < P.W && j < P.H) {
     PixelOut r;
-    render_pixel_de<NORM>(P, i, j, r, iters);
+    render_pixel_de<NORM, AXIS>(P, cv, i, j, r, iters);
     write_pixel(out, (int64_t)j * P.W + i, r);
   }
   if (out.iters) wave_add_u64(out.iters, iters);
@@ -153,10 +195,20 @@ __global__ __launch_bounds__(256) void render_de_kernel(KParams P, KOut out) {
 
 hipError_t launch_render_de(const KParams &P, const KOut &out, hipStream_t s) {
   dim3 grid((P.W + 15) / 16, (P.H + 15) / 16);
-  if (P.norm == 0)
-    hipLaunchKernelGGL(render_de_kernel<0>, grid, dim3(256), 0, s, P, out);
-  else
-    hipLaunchKernelGGL(render_de_kernel<1>, grid, dim3(256), 0, s, P, out);
+  const bool axis = P.axis_slice != 0;
+#define DQJ_DE_DIRECT(NM, AX) hipLaunchKernelGGL((render_de_kernel<NM, AX>), grid, dim3(256), 0, s, P, out)
+  if (P.norm == 0) {
+    if (axis)
+      DQJ_DE_DIRECT(0, true);
+    else
+      DQJ_DE_DIRECT(0, false);
+  } else {
+    if (axis)
+      DQJ_DE_DIRECT(1, true);
+    else
+      DQJ_DE_DIRECT(1, false);
+  }
+#undef DQJ_DE_DIRECT
   return hipGetLastError();
 }
 
@@ -172,25 +224,6 @@ using namespace persist;
 namespace {
 
 enum { DE_IDLE = 0, DE_MARCH = 1, DE_BISECT = 2, DE_NORMAL = 3 };
-
-template <bool AXIS>
-__device__ __forceinline__ void de_start(const KParams &P, float x, float y, float w, DQ<float> &z,
-                                         float &s) {
-  if (AXIS) {
-    z = DQ<float>{x, y, w, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    s = fmaf(w, w, y * y);
-  } else {
-    z = slice_map<float>(P, x, y, w);
-    s = vec_s(z);
-  }
-}
-
-template <int NORM>
-__device__ __forceinline__ float norm2_of(const DQ<float> &z, float s) {
-  float n2 = fmaf(z.a0, z.a0, s);
-  if (NORM == 0) n2 = fmaf(z.b3, z.b3, fmaf(z.b2, z.b2, fmaf(z.b1, z.b1, fmaf(z.b0, z.b0, n2))));
-  return n2;
-}
 
 }  // namespace
 
@@ -221,9 +254,9 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
   int next_r = 0;
   bool have_tile = false, pending = false, exhausted = false;
   uint32_t pend_tile = 0;
-  float c[8];
+  float cv[8];   // per-lane copies of c (vector-register operands issue faster)
 #pragma unroll
-  for (int q = 0; q < 8; ++q) c[q] = 0.0f;
+  for (int q = 0; q < 8; ++q) cv[q] = 0.0f;
   float R2 = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
   float inv_r2 = 0.0f, l4r2 = 0.0f, eps = 0.0f, smin = 0.0f, smax = 0.0f;
   int N = 1, S = 1;
@@ -247,7 +280,7 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
     ++trip;
     // ---- one update on every lane, the derivative norm carried along
     D = D * (n2prev * inv_r2);
-    const float n2 = dq_update<NORM>(z, s, c);
+    const float n2 = de_update<NORM>(z, s, cv);
     n2prev = n2;
     const bool esc = n2 > R2;
     const bool expired = (int)(trip - dl) >= 0;
@@ -257,9 +290,7 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
     float de = 0.0f;
     if (esc && phase == DE_MARCH) {
       const int m = N - (int)(dl - trip);
-      const float l2n = __builtin_amdgcn_logf(n2);
-      const float q = 0.5f * (l2n - __builtin_amdgcn_logf(D) - (float)m * l4r2);
-      de = 0.25f * 0.69314718f * l2n * __builtin_amdgcn_exp2f(q);
+      de = de_estimate(n2, D, m, l4r2);
       const float tn = t + fminf(fmaxf(de, smin), smax);
       fast = de >= eps && tn <= t1 && k + 1 < S;
       if (fast) {
@@ -396,7 +427,7 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
           frame = f;
           if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) c[q] = uniform_f(F->P.c[q]);
+          for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(uniform_f(F->P.c[q]));
           R2 = uniform_f(F->P.R2);
           N = (int)uniform((uint32_t)F->P.N);
           S = (int)uniform((uint32_t)F->P.S);
