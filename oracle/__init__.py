@@ -47,6 +47,11 @@ class _Params(C.Structure):
         ("de_hit_eps", C.c_double),
         ("de_min_step", C.c_double),
         ("de_max_step", C.c_double),
+        ("algebra", C.c_int32),
+        ("normal_mode", C.c_int32),
+        ("k_specular", C.c_double),
+        ("shininess", C.c_double),
+        ("cull_radius", C.c_double),
     ]
 
 
@@ -86,6 +91,10 @@ def lib():
         L.dqjo_scan_ray.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                     C.POINTER(C.c_uint8)]
         L.dqjo_scan_ray.restype = C.c_int32
+        L.dqjo_classify_grid.argtypes = [P, C.c_int32, C.c_int32, C.c_int32,
+                                         C.POINTER(C.c_int64), C.c_int64, C.POINTER(C.c_uint8),
+                                         C.POINTER(C.c_int32), C.c_int32]
+        L.dqjo_classify_grid.restype = C.c_uint64
         L.dqjo_params_size.restype = C.c_uint32
         _lib = L
     return _lib
@@ -116,6 +125,11 @@ def make_params(p) -> _Params:
     s.de_hit_eps = getattr(p, "de_hit_eps", 1e-4)
     s.de_min_step = getattr(p, "de_min_step", 1e-4)
     s.de_max_step = getattr(p, "de_max_step", 0.25)
+    s.algebra = getattr(p, "algebra", 0)
+    s.normal_mode = getattr(p, "normal_mode", 0)
+    s.k_specular = getattr(p, "k_specular", 0.0)
+    s.shininess = getattr(p, "shininess", 16.0)
+    s.cull_radius = getattr(p, "cull_radius", 0.0)
     return s
 
 
@@ -248,6 +262,29 @@ def render(p, pixels: Optional[Sequence[int]] = None, nthreads: int = 0) -> Dict
             "shade": shade.reshape(shape), "normal": normal.reshape(shape + (3,)),
             "first_hit": first_hit.reshape(shape), "iters": iters.reshape(shape),
             "total_iters": int(total)}
+
+
+def classify_grid(p, nx: int, ny: int, nz: int, voxels: Optional[Sequence[int]] = None,
+                  nthreads: int = 0) -> Dict[str, np.ndarray]:
+    """Classify the voxel centres of the box (all of them, shape (nz, ny, nx), or the
+    listed linear voxel indices (k*ny + j)*nx + i, flat): inside, escape index m (0 when
+    inside) and the total update count."""
+    sp = make_params(p)
+    if voxels is None:
+        n = nx * ny * nz
+        vptr = None
+        shape = (nz, ny, nx)
+    else:
+        vox = np.ascontiguousarray(np.asarray(voxels, dtype=np.int64))
+        n = vox.shape[0]
+        vptr = vox.ctypes.data_as(C.POINTER(C.c_int64))
+        shape = (n,)
+    inside = np.zeros(n, np.uint8)
+    m = np.zeros(n, np.int32)
+    total = lib().dqjo_classify_grid(C.byref(sp), int(nx), int(ny), int(nz), vptr, n,
+                                     inside.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                     m.ctypes.data_as(C.POINTER(C.c_int32)), int(nthreads))
+    return {"inside": inside.reshape(shape), "m": m.reshape(shape), "total_iters": int(total)}
 
 
 def scan_ray(p, i: int, j: int, ta: float, tb: float, n: int = 64):

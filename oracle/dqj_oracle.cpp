@@ -7,6 +7,7 @@
 
 #include <math.h>
 #include <string.h>
+#include <vector>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -82,6 +83,22 @@ static void dq_step(const double z[8], const double c[8], double out[8]) {
   dqjo_dq_add(sq, c, out);
 }
 
+// The square as printed with Eq. dqjulia2, component by component: q_a^2 + q_b^2 e, each
+// quaternion squared with the Hamilton product. Offered as an alternative algebra.
+static void dq_step_componentwise(const double z[8], const double c[8], double out[8]) {
+  double sq[8];
+  dqjo_quat_mul(z, z, sq);
+  dqjo_quat_mul(z + 4, z + 4, sq + 4);
+  dqjo_dq_add(sq, c, out);
+}
+
+static void step_for(const dqjo_params *p, const double z[8], double out[8]) {
+  if (p->algebra == 1)
+    dq_step_componentwise(z, p->c, out);
+  else
+    dq_step(z, p->c, out);
+}
+
 void dqjo_orbit(const double z0[8], const double c[8], int32_t n, double out[8]) {
   double z[8];
   memcpy(z, z0, sizeof z);
@@ -113,7 +130,7 @@ int32_t dqjo_classify(const dqjo_params *p, const double z0[8], int32_t *m,
   int32_t inside = 1;
   int32_t n = 0;
   for (n = 1; n <= p->max_iter; ++n) {
-    dq_step(z, p->c, z);
+    step_for(p, z, z);
     n2 = escape_norm2(p, z);
     if (n2 > R2) {
       inside = 0;
@@ -140,7 +157,7 @@ int32_t dqjo_distance(const dqjo_params *p, const double z0[8], int32_t *m, doub
   double dz = 1.0;                    // |z'_0|
   for (int32_t n = 1; n <= p->max_iter; ++n) {
     dz = 2.0 * sqrt(n2) * dz;         // |z'_n| from |z_{n-1}| and |z'_{n-1}|
-    dq_step(z, p->c, z);
+    step_for(p, z, z);
     n2 = escape_norm2(p, z);
     if (n2 > R2) {
       const double r = sqrt(n2);
@@ -229,6 +246,20 @@ int32_t dqjo_ray(const dqjo_params *p, int32_t i, int32_t j, double o[3], double
     if (tb < tf) tf = tb;
   }
   if (tn > tf) return 0;
+  // Bounding sphere about the origin (section "Ray-Marching": rays meet a sphere that
+  // encloses the fractal first): |o + t d|^2 <= r^2 for t in [-b - sqrt(q), -b + sqrt(q)],
+  // b = o.d, q = b^2 - (|o|^2 - r^2); no real root misses.
+  if (p->cull_radius > 0.0) {
+    const double b = o[0] * d[0] + o[1] * d[1] + o[2] * d[2];
+    const double oo = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+    const double q = b * b - (oo - p->cull_radius * p->cull_radius);
+    if (q < 0.0) return 0;
+    const double sq = sqrt(q);
+    const double sa = -b - sq, sb = -b + sq;
+    if (sa > tn) tn = sa;
+    if (sb < tf) tf = sb;
+    if (tn > tf) return 0;
+  }
   *t0 = tn;
   *t1 = tf;
   return 1;
@@ -259,6 +290,25 @@ struct PixelResult {
   int32_t first_hit;
   uint64_t iters;
 };
+
+// Eq. phong with one directional light of unit intensity: ambient, diffuse
+// k_d max(0, n.l) and specular k_s max(0, r.v)^s with the reflected light vector
+// r = 2 n (n.l) - l and v = -d pointing back to the eye, the specular term only where
+// the light reaches the surface (n.l > 0); the sum is clamped to [0, 1].
+static double phong(const dqjo_params *p, const double n[3], const double d[3]) {
+  double l[3] = {p->light_dir[0], p->light_dir[1], p->light_dir[2]};
+  normalize3(l);
+  double ndl = n[0] * l[0] + n[1] * l[1] + n[2] * l[2];
+  double s = p->k_ambient + p->k_diffuse * (ndl > 0.0 ? ndl : 0.0);
+  if (p->k_specular > 0.0 && ndl > 0.0) {
+    double rv = 0.0;
+    for (int k = 0; k < 3; ++k) rv += (2.0 * n[k] * ndl - l[k]) * (-d[k]);
+    if (rv > 0.0) s += p->k_specular * pow(rv, p->shininess);
+  }
+  if (s < 0.0) s = 0.0;
+  if (s > 1.0) s = 1.0;
+  return s;
+}
 
 static PixelResult render_pixel(const dqjo_params *p, int32_t i, int32_t j) {
   PixelResult res;
@@ -352,6 +402,12 @@ static PixelResult render_pixel(const dqjo_params *p, int32_t i, int32_t j) {
     thit = 0.5 * (lo + hi);
   }
   const double ph[3] = {o[0] + thit * d[0], o[1] + thit * d[1], o[2] + thit * d[2]};
+  res.mask = 1;
+  res.depth = thit;
+  res.first_hit = kstar;
+  // The four-neighbour normal needs the neighbouring pixels' hits: dqjo_render forms it
+  // and the shade after every pixel has its depth; no update is spent on it here.
+  if (p->normal_mode == 1) return res;
 
   // Central differences of the potential along the world axes.
   double g[3];
@@ -378,40 +434,95 @@ static PixelResult render_pixel(const dqjo_params *p, int32_t i, int32_t j) {
     n[2] = -d[2];
   }
 
-  // Eq. phong, ambient and diffuse terms, one directional light, clamped to [0, 1].
-  double l[3] = {p->light_dir[0], p->light_dir[1], p->light_dir[2]};
-  normalize3(l);
-  double ndl = n[0] * l[0] + n[1] * l[1] + n[2] * l[2];
-  if (ndl < 0.0) ndl = 0.0;
-  double s = p->k_ambient + p->k_diffuse * ndl;
-  if (s < 0.0) s = 0.0;
-  if (s > 1.0) s = 1.0;
-
-  res.mask = 1;
-  res.depth = thit;
-  res.shade = s;
+  res.shade = phong(p, n, d);
   res.normal[0] = n[0];
   res.normal[1] = n[1];
   res.normal[2] = n[2];
-  res.first_hit = kstar;
   return res;
+}
+
+// Paragraph "Lighting/Illumination": a normal from the surface through the hit points
+// of the four neighbouring pixels (left, right, above, below). dep[0..4] are the depths
+// of pixel (i, j) and of (i-1, j), (i+1, j), (i, j-1), (i, j+1) (row 0 at the top; +inf
+// for a miss or a pixel outside the image). Along each image axis the tangent is the
+// central difference of the neighbours' hit points when both hit, else the one-sided
+// difference with the pixel's own hit; the normal is the normalised cross product of the
+// horizontal tangent (towards the right) and the vertical tangent (towards the top),
+// turned to face the eye. A missing tangent or a vanishing product gives -d.
+static void neighbour_normal(const dqjo_params *p, int32_t i, int32_t j, const double dep[5],
+                             double n[3], double dc[3]) {
+  const int32_t ni[5] = {i, i - 1, i + 1, i, i};
+  const int32_t nj[5] = {j, j, j, j - 1, j + 1};
+  double P[5][3];
+  int hit[5];
+  for (int q = 0; q < 5; ++q) {
+    hit[q] = isfinite(dep[q]) ? 1 : 0;
+    double o[3], d[3], t0, t1;
+    const int32_t ii = ni[q] < 0 ? 0 : (ni[q] >= p->width ? p->width - 1 : ni[q]);
+    const int32_t jj = nj[q] < 0 ? 0 : (nj[q] >= p->height ? p->height - 1 : nj[q]);
+    dqjo_ray(p, ii, jj, o, d, &t0, &t1);
+    if (q == 0) memcpy(dc, d, sizeof(double) * 3);
+    for (int k = 0; k < 3; ++k) P[q][k] = hit[q] ? o[k] + dep[q] * d[k] : 0.0;
+  }
+  double tx[3], ty[3];
+  int hx = 1, hy = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (hit[1] && hit[2]) tx[k] = P[2][k] - P[1][k];
+    else if (hit[2]) tx[k] = P[2][k] - P[0][k];
+    else if (hit[1]) tx[k] = P[0][k] - P[1][k];
+    else hx = 0;
+    if (hit[3] && hit[4]) ty[k] = P[3][k] - P[4][k];
+    else if (hit[3]) ty[k] = P[3][k] - P[0][k];
+    else if (hit[4]) ty[k] = P[0][k] - P[4][k];
+    else hy = 0;
+  }
+  double c[3] = {0.0, 0.0, 0.0};
+  if (hx && hy) cross3(tx, ty, c);
+  const double len = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  if (hx && hy && len > 0.0 && isfinite(len)) {
+    for (int k = 0; k < 3; ++k) n[k] = c[k] / len;
+    if (n[0] * dc[0] + n[1] * dc[1] + n[2] * dc[2] > 0.0)
+      for (int k = 0; k < 3; ++k) n[k] = -n[k];
+  } else {
+    for (int k = 0; k < 3; ++k) n[k] = -dc[k];
+  }
+}
+
+static double depth_of(const dqjo_params *p, int32_t i, int32_t j) {
+  if (i < 0 || j < 0 || i >= p->width || j >= p->height) return INFINITY;
+  return render_pixel(p, i, j).depth;
 }
 
 uint64_t dqjo_render(const dqjo_params *p, const int64_t *pix, int64_t npix, uint8_t *mask,
                      double *depth, double *shade, double *normal, int32_t *first_hit,
                      uint64_t *iters, int32_t nthreads) {
-  const int64_t W = p->width;
-  const int64_t total = pix ? npix : W * (int64_t)p->height;
+  const int64_t W = p->width, H = p->height;
+  const int64_t total = pix ? npix : W * H;
   uint64_t sum = 0;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
   (void)nthreads;
 #endif
+  // Four-neighbour normals of a full frame read the frame's own depth buffer.
+  std::vector<double> frame_depth;
+  if (p->normal_mode == 1 && !pix) frame_depth.assign((size_t)total, INFINITY);
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : sum)
   for (int64_t q = 0; q < total; ++q) {
     const int64_t idx = pix ? pix[q] : q;
-    const PixelResult r = render_pixel(p, (int32_t)(idx % W), (int32_t)(idx / W));
+    const int32_t i = (int32_t)(idx % W), j = (int32_t)(idx / W);
+    PixelResult r = render_pixel(p, i, j);
+    if (p->normal_mode == 1) {
+      if (!pix) {
+        frame_depth[(size_t)q] = r.depth;
+      } else if (r.mask) {
+        const double dep[5] = {r.depth, depth_of(p, i - 1, j), depth_of(p, i + 1, j),
+                               depth_of(p, i, j - 1), depth_of(p, i, j + 1)};
+        double dc[3];
+        neighbour_normal(p, i, j, dep, r.normal, dc);
+        r.shade = phong(p, r.normal, dc);
+      }
+    }
     if (mask) mask[q] = r.mask;
     if (depth) depth[q] = r.depth;
     if (shade) shade[q] = r.shade;
@@ -423,6 +534,53 @@ uint64_t dqjo_render(const dqjo_params *p, const int64_t *pix, int64_t npix, uin
     if (first_hit) first_hit[q] = r.first_hit;
     if (iters) iters[q] = r.iters;
     sum += r.iters;
+  }
+  if (p->normal_mode == 1 && !pix) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < total; ++q) {
+      if (!isfinite(frame_depth[(size_t)q])) continue;
+      const int32_t i = (int32_t)(q % W), j = (int32_t)(q / W);
+      auto at = [&](int32_t ii, int32_t jj) {
+        return (ii < 0 || jj < 0 || ii >= W || jj >= H) ? INFINITY
+                                                        : frame_depth[(size_t)(jj * W + ii)];
+      };
+      const double dep[5] = {frame_depth[(size_t)q], at(i - 1, j), at(i + 1, j), at(i, j - 1),
+                             at(i, j + 1)};
+      double n[3], dc[3];
+      neighbour_normal(p, i, j, dep, n, dc);
+      if (shade) shade[q] = phong(p, n, dc);
+      if (normal)
+        for (int k = 0; k < 3; ++k) normal[3 * q + k] = n[k];
+    }
+  }
+  return sum;
+}
+
+// Dense voxel grid (the voxel prototype of section "Ray-Marching"): voxel centres of the
+// box, slice-mapped and classified.
+uint64_t dqjo_classify_grid(const dqjo_params *p, int32_t nx, int32_t ny, int32_t nz,
+                            const int64_t *idx, int64_t nidx, uint8_t *inside, int32_t *m,
+                            int32_t nthreads) {
+  const int64_t total = idx ? nidx : (int64_t)nx * ny * nz;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+  uint64_t sum = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : sum)
+  for (int64_t q = 0; q < total; ++q) {
+    const int64_t v = idx ? idx[q] : q;
+    const int64_t i = v % nx, j = (v / nx) % ny, k = v / ((int64_t)nx * ny);
+    const double x[3] = {
+        p->box_min[0] + ((double)i + 0.5) * (p->box_max[0] - p->box_min[0]) / nx,
+        p->box_min[1] + ((double)j + 0.5) * (p->box_max[1] - p->box_min[1]) / ny,
+        p->box_min[2] + ((double)k + 0.5) * (p->box_max[2] - p->box_min[2]) / nz};
+    int32_t mi;
+    const int32_t in = classify_world(p, x, &mi);
+    if (inside) inside[q] = (uint8_t)in;
+    if (m) m[q] = in ? 0 : mi;
+    sum += (uint64_t)mi;
   }
   return sum;
 }

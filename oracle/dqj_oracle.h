@@ -18,7 +18,11 @@
  *   - fixed-step ray march over the bounding box (section "Ray-Marching"),
  *     bisection of the first inside/outside crossing, central-difference normal of
  *     a smooth escape potential (section "Lighting/Illumination"), and the ambient +
- *     diffuse terms of Eq. phong.
+ *     diffuse terms of Eq. phong;
+ *   - extensions: the distance-estimate march of Eq. distfract2, the bounding
+ *     sphere, the specular term of Eq. phong, a normal from the four neighbouring
+ *     pixels' hits, the component-wise square printed with Eq. dqjulia2, and the
+ *     dense voxel grid of the paper's first prototype.
  *
  * Readings where the paper is silent or garbled are listed in the oracle source
  * next to the code that takes them.
@@ -50,6 +54,10 @@ typedef struct dqjo_params {
   double k_ambient, k_diffuse;
   int32_t march;               /* 0: fixed steps, 1: distance-estimate steps */
   double de_hit_eps, de_min_step, de_max_step;
+  int32_t algebra;             /* 0: a^2 + (ab + ba)e, 1: a^2 + b^2 e (printed form) */
+  int32_t normal_mode;         /* 0: potential gradient, 1: four neighbouring pixels */
+  double k_specular, shininess;    /* specular term of Eq. phong */
+  double cull_radius;          /* bounding sphere about the origin, 0: none */
 } dqjo_params;
 
 /* ---- algebra (Appendix) ---- */
@@ -75,6 +83,17 @@ int32_t dqjo_classify(const dqjo_params *p, const double z0[8], int32_t *m,
 int32_t dqjo_distance(const dqjo_params *p, const double z0[8], int32_t *m, double *de);
 void dqjo_classify_many(const dqjo_params *p, const double *pts, int64_t n,
                         uint8_t *inside, int32_t *m, double *norm2, double *zfinal);
+
+/* Dense grid classification: the nx x ny x nz voxel centres
+ * x_i = box_min + (i + 1/2)(box_max - box_min)/n of the box, each mapped through the
+ * slice and classified. Voxel (i, j, k) is entry (k ny + j) nx + i. If idx is NULL every
+ * voxel is classified and outputs are full grids; otherwise only the nidx listed voxel
+ * indices, with outputs indexed by list position. inside: 1/0; m: escape index, 0 when
+ * inside. Returns the total number of updates (the escape index, or max_iter when
+ * inside, summed). Outputs may be NULL. */
+uint64_t dqjo_classify_grid(const dqjo_params *p, int32_t nx, int32_t ny, int32_t nz,
+                            const int64_t *idx, int64_t nidx, uint8_t *inside, int32_t *m,
+                            int32_t nthreads);
 
 /* World point -> R^8 through the slice. */
 void dqjo_slice_map(const dqjo_params *p, const double x[3], double z0[8]);

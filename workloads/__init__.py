@@ -39,6 +39,12 @@ PREC_FP64 = 2
 MARCH_FIXED = 0       # S fixed steps over the box segment, then bisection
 MARCH_DE = 1          # distance-estimate steps (the paper's own march)
 
+ALGEBRA_DUAL = 0           # (a + b e)^2 = a^2 + (ab + ba) e, the product rule
+ALGEBRA_COMPONENTWISE = 1  # a^2 + b^2 e, the form printed with the iteration
+
+NORMAL_POTENTIAL = 0    # central differences of the escape potential
+NORMAL_NEIGHBOUR4 = 1   # from the four neighbouring pixels' hit points
+
 
 def f32(x: float) -> float:
     """Round one FP64 value to the nearest FP32 value (returned as a Python float)."""
@@ -101,6 +107,11 @@ class Params:
     de_hit_eps: float = 1e-4
     de_min_step: float = 1e-4
     de_max_step: float = 0.25
+    algebra: int = ALGEBRA_DUAL
+    normal_mode: int = NORMAL_POTENTIAL
+    k_specular: float = 0.0
+    shininess: float = 16.0
+    cull_radius: float = 0.0
 
     def __post_init__(self):
         self.c = f32v(self.c)
@@ -120,6 +131,9 @@ class Params:
         self.de_hit_eps = f32(self.de_hit_eps)
         self.de_min_step = f32(self.de_min_step)
         self.de_max_step = f32(self.de_max_step)
+        self.k_specular = f32(self.k_specular)
+        self.shininess = f32(self.shininess)
+        self.cull_radius = f32(self.cull_radius)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
