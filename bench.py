@@ -413,6 +413,84 @@ def bench_de(args, dqj, workloads, torch):
     return line
 
 
+def bench_voxel(args, dqj, workloads, torch):
+    """Dense voxel-grid classification (dqj_classify_grid): the 1024^3 voxel centres of
+    the box for the paper's high-detail constant (max_iter 15), against the FP64 oracle's
+    count of the updates classification runs (tests/golden/ialg_voxel_1024.json)."""
+    import numpy as np
+    p, dims = workloads.voxel_1024()
+    with open(os.path.join(ROOT, "tests", "golden", "ialg_voxel_1024.json")) as f:
+        gold = json.load(f)
+    assert [round(x, 7) for x in gold["c"]] == [round(x, 7) for x in p.c], "golden/c mismatch"
+    ialg = int(gold["total_iters"])
+    nvox = int(np.prod(dims))
+    stream = torch.cuda.current_stream()
+    mask = torch.empty(dims[::-1], dtype=torch.uint8, device="cuda")
+    iters = torch.zeros((1,), dtype=torch.int64, device="cuda")
+    dqj.classify_grid(p, *dims, mask=mask, iters=iters, stream=stream)
+    torch.cuda.synchronize()
+    counted = int(iters.item())
+    inside = int(mask.sum().item())
+    for _ in range(args.warmup):
+        dqj.classify_grid(p, *dims, mask=mask, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        dqj.classify_grid(p, *dims, mask=mask, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    achieved = FLOPS_PER_UPDATE * ialg / (ev_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": ialg / (ms * 1e-3), "unit": "Julia iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "voxel_1024: the 1024^3 voxel centres of the box [-1.5, 1.5]^3, "
+                               "identity slice, the paper's high-detail constant, max_iter 15, "
+                               "one dqj_classify_grid per step",
+                   "nx": dims[0], "ny": dims[1], "nz": dims[2], "max_iter": p.max_iter},
+        "voxels_per_s": nvox / (ms * 1e-3),
+        "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "classify_grid_kernel", "kernel_ms_per_step": ev_ms,
+                     "flops_per_update": FLOPS_PER_UPDATE,
+                     "algorithmic_bytes_per_launch": nvox,
+                     "frac_of_measured_fmac_issue": achieved / FP32_FMAC_ISSUE_TFLOPS},
+        "ialg_per_step": ialg, "ialg_source": "FP64 oracle, tests/golden/ialg_voxel_1024.json",
+        "gpu_counted_iters_per_step": counted, "inside_voxels": inside,
+        "inside_voxels_oracle": int(gold["inside"]),
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_grid(p, dims, args.cpu_seconds)
+    return line
+
+
+def cpu_baseline_grid(p, dims, target_s):
+    """The FP64 oracle on a bounded random sample of the grid's voxels."""
+    import numpy as np
+    import oracle
+    nthreads = cpu_threads()
+    rng = np.random.default_rng(12345)
+    n = int(np.prod(dims))
+    pilot = np.sort(rng.integers(0, n, 200000))
+    t = time.perf_counter()
+    oracle.classify_grid(p, *dims, voxels=pilot, nthreads=nthreads)
+    rate = pilot.size / max(time.perf_counter() - t, 1e-6)
+    k = int(min(max(target_s * rate, 100000), 64 * 1024 * 1024))
+    sample = np.sort(rng.integers(0, n, k))
+    t = time.perf_counter()
+    it = oracle.classify_grid(p, *dims, voxels=sample, nthreads=nthreads)["total_iters"]
+    dt = time.perf_counter() - t
+    return {"value": it / dt, "unit": "Julia iters/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{k} uniformly sampled voxels of the {dims[0]}x{dims[1]}x{dims[2]} grid "
+                      f"({it} updates, {dt:.1f} s, FP64)", "seconds": round(dt, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,7 +503,8 @@ def main():
                     help="length of the served request stream (0: skip; the full stream is 60)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--capacity-requests", type=int, default=300)
-    ap.add_argument("--workload", choices=["plain_1024", "split_1080p", "sweep_256", "de_1024"],
+    ap.add_argument("--workload", choices=["plain_1024", "split_1080p", "sweep_256", "de_1024",
+                                           "voxel_1024"],
                     default="plain_1024")
     ap.add_argument("--error-pixels", type=int, default=4000)
     ap.add_argument("--sweep-frames", type=int, default=4096)
@@ -454,7 +533,8 @@ def main():
 
     if args.workload != "plain_1024":
         torch.cuda.set_device(0)
-        fn = {"split_1080p": bench_split, "sweep_256": bench_sweep, "de_1024": bench_de}[args.workload]
+        fn = {"split_1080p": bench_split, "sweep_256": bench_sweep, "de_1024": bench_de,
+              "voxel_1024": bench_voxel}[args.workload]
         print(json.dumps(fn(args, dqj, workloads, torch)), flush=True)
         return
 
@@ -539,7 +619,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP32_PEAK_TFLOPS,
                      "traffic": recorded_traffic() if args.kernel == "refill" else None,
-                     "kernel": "render_refill_kernel" if args.kernel == "refill" else
+                     "kernel": "render_refill_batch_kernel" if args.kernel == "refill" else
                                "render_direct_kernel",
                      "kernel_ms_per_launch": ev_ms,
                      "flops_per_launch": FLOPS_PER_UPDATE * ialg,

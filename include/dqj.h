@@ -96,9 +96,32 @@ typedef struct dqj_params {
   double de_hit_eps;           /* DE: > 0, world units */
   double de_min_step;          /* DE: > 0 */
   double de_max_step;          /* DE: >= de_min_step */
+  /* Algebra of the square (section "Dual-Quaternion Julia Sets"). DUAL: the square the
+   * dual-quaternion product gives, (a + b e)^2 = a^2 + (ab + ba) e. COMPONENTWISE: the form
+   * printed with Eq. dqjulia2, a^2 + b^2 e (its dual orbit does not depend on the point
+   * when the slice keeps b_0 = 0). COMPONENTWISE is offered by dqj_classify_grid only;
+   * renders return DQJ_E_UNSUPPORTED for it. */
+  int32_t algebra;             /* DQJ_ALGEBRA_DUAL (0) or DQJ_ALGEBRA_COMPONENTWISE (1) */
+  /* Normal estimate (paragraph "Lighting/Illumination"). POTENTIAL: central differences of
+   * the escape potential ln(max(||z_m||^2, 1e-30)) 2^-m at p +- normal_h along each axis.
+   * NEIGHBOUR4: from the hit points of the four neighbouring pixels (above, below, left,
+   * right), n = normalize((P_right - P_left) x (P_up - P_down)) with one-sided differences
+   * where a neighbour misses and -d where a whole pair misses, facing the eye; dqj_render
+   * only (batches and the server return DQJ_E_UNSUPPORTED). */
+  int32_t normal_mode;         /* DQJ_NORMAL_POTENTIAL (0) or DQJ_NORMAL_NEIGHBOUR4 (1) */
+  /* Specular term of Eq. phong: k_specular * max(0, r . v)^shininess with
+   * r = 2 n (n . l) - l and v = -d (towards the eye), added where n . l > 0. */
+  double k_specular;           /* >= 0; 0 leaves the ambient + diffuse shade */
+  double shininess;            /* >= 1 */
+  /* Bounding sphere (section "Ray-Marching"): rays are clipped to the sphere of this
+   * radius about the world origin as well as to the box, so rays that miss it are
+   * discarded before any update. 0 disables the sphere. */
+  double cull_radius;          /* >= 0 */
 } dqj_params;
 
 enum { DQJ_MARCH_FIXED = 0, DQJ_MARCH_DE = 1 };
+enum { DQJ_ALGEBRA_DUAL = 0, DQJ_ALGEBRA_COMPONENTWISE = 1 };
+enum { DQJ_NORMAL_POTENTIAL = 0, DQJ_NORMAL_NEIGHBOUR4 = 1 };
 
 /* Per-pixel ray flags written to dqj_frame_out.flags (bit set). */
 enum {
@@ -178,6 +201,22 @@ dqj_status dqj_batch_plan_destroy(dqj_batch_plan *plan);   /* waits for its work
 dqj_status dqj_classify_points(const void *pts_dev, int32_t n, int32_t precision,
                                const dqj_params *params, int32_t *escape_iter_dev,
                                float *final_norm2_dev, void *hip_stream);
+
+/* Dense voxel-grid classification: the paper's first prototype (section "Ray-Marching",
+ * the voxel-versus-ray-traced figure) as a throughput entry point. The nx x ny x nz voxel
+ * centres x_i = box_min + (i + 1/2)(box_max - box_min)/n of params' box are mapped through
+ * the slice and classified with params' c, max_iter, escape_radius, norm and algebra (the
+ * camera, march and shading fields are validated but unused); precision must be
+ * DQJ_PREC_FP32. Sizes 1..4096 per axis.
+ * Outputs (device pointers, caller-owned, voxel (i, j, k) at (k ny + j) nx + i):
+ *   mask_dev (required, u8): 1 inside, 0 outside;
+ *   escape_dev (optional, i32): escape index 1..max_iter, 0 when inside;
+ *   iters_dev (optional, one u64): updates run (escape index, or max_iter inside), added.
+ * Stream-ordered; returns after the launch. Errors: DQJ_E_INVALID (sizes, NULL mask,
+ * parameters), DQJ_E_UNSUPPORTED (precision), DQJ_E_DEVICE. */
+dqj_status dqj_classify_grid(const dqj_params *params, int32_t nx, int32_t ny, int32_t nz,
+                             uint8_t *mask_dev, int32_t *escape_dev,
+                             unsigned long long *iters_dev, void *hip_stream);
 
 /* ---- Request server (continuous batching) -------------------------------------
  * Requests of any size, Julia constant and max_iter are queued as they are

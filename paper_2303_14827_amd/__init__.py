@@ -19,6 +19,8 @@ E_INVALID, E_NOMEM, E_BUDGET, E_QUEUE_FULL, E_DEVICE = -1, -2, -3, -4, -5
 E_TIMEOUT, E_CANCELLED, E_UNSUPPORTED, E_STATE = -6, -7, -8, -9
 SERVE_FAIR, SERVE_OLDEST = 0, 1
 MARCH_FIXED, MARCH_DE = 0, 1
+ALGEBRA_DUAL, ALGEBRA_COMPONENTWISE = 0, 1
+NORMAL_POTENTIAL, NORMAL_NEIGHBOUR4 = 0, 1
 
 NORM_EUCLID8, NORM_REALPART = 0, 1
 PREC_FP32, PREC_SPLIT, PREC_FP64 = 0, 1, 2
@@ -61,6 +63,11 @@ class dqj_params(C.Structure):
         ("de_hit_eps", C.c_double),
         ("de_min_step", C.c_double),
         ("de_max_step", C.c_double),
+        ("algebra", C.c_int32),
+        ("normal_mode", C.c_int32),
+        ("k_specular", C.c_double),
+        ("shininess", C.c_double),
+        ("cull_radius", C.c_double),
     ]
 
 
@@ -167,6 +174,8 @@ _SIGS = {
     "dqj_batch_plan_destroy": (C.c_int32, [C.c_void_p]),
     "dqj_classify_points": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(dqj_params),
                                         C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dqj_classify_grid": (C.c_int32, [C.POINTER(dqj_params), C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dqj_device_info_get": (C.c_int32, [C.c_int32, C.POINTER(dqj_device_info)]),
     "dqj_autotune": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out), C.c_int32,
                                  C.c_char_p, C.POINTER(dqj_schedule)]),
@@ -236,6 +245,11 @@ def make_params(p) -> dqj_params:
     s.de_hit_eps = getattr(p, "de_hit_eps", 1e-4)
     s.de_min_step = getattr(p, "de_min_step", 1e-4)
     s.de_max_step = getattr(p, "de_max_step", 0.25)
+    s.algebra = getattr(p, "algebra", 0)
+    s.normal_mode = getattr(p, "normal_mode", 0)
+    s.k_specular = getattr(p, "k_specular", 0.0)
+    s.shininess = getattr(p, "shininess", 16.0)
+    s.cull_radius = getattr(p, "cull_radius", 0.0)
     return s
 
 
@@ -359,6 +373,30 @@ def classify_points(pts, p, precision: int = PREC_FP32, stream=None):
                                      C.c_void_p(esc.data_ptr()), C.c_void_p(n2.data_ptr()),
                                      _stream(stream)))
     return esc, n2
+
+
+def classify_grid(p, nx: int, ny: int, nz: int, mask=None, escape=None, iters=None,
+                  extras: bool = False, stream=None) -> Dict:
+    """Classify the nx x ny x nz voxel centres of p's box (dqj_classify_grid). Outputs
+    are device tensors of shape (nz, ny, nx): ``mask`` (u8) and, with ``extras``, the
+    escape index (i32) and a one-element update counter (int64, added to)."""
+    import torch
+    if mask is None:
+        mask = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    if extras and escape is None:
+        escape = torch.empty((nz, ny, nx), dtype=torch.int32, device="cuda")
+    if extras and iters is None:
+        iters = torch.zeros((1,), dtype=torch.int64, device="cuda")
+    sp = make_params(p)
+    ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    _check(lib().dqj_classify_grid(C.byref(sp), nx, ny, nz, ptr(mask), ptr(escape), ptr(iters),
+                                   _stream(stream)))
+    out = {"mask": mask}
+    if escape is not None:
+        out["escape"] = escape
+    if iters is not None:
+        out["iters"] = iters
+    return out
 
 
 def _result_dict(r: dqj_request_result) -> Dict:

@@ -118,6 +118,8 @@ extern "C" dqj_status dqj_autotune(const dqj_params *params, const dqj_frame_out
     for (int32_t i = 0; i < n; ++i) {
       st = validate_params(params + i);
       if (st != DQJ_OK) return st;
+      st = check_render_modes(params[i], false);
+      if (st != DQJ_OK) return st;
       st = validate_out(outs + i);
       if (st != DQJ_OK) return st;
     }

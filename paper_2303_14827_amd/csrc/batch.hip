@@ -38,6 +38,8 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
   for (int32_t i = 0; i < n; ++i) {
     dqj_status st = validate_params(params + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
+    st = check_render_modes(params[i], false);
+    if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
     st = validate_out(outs + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
     if (params[i].march != DQJ_MARCH_FIXED)

@@ -194,7 +194,53 @@ __device__ __forceinline__ void pixel_dir(const KParams &P, int i, int j, float 
   d[2] = v[2] * inv;
 }
 
-// Slab clip of the ray eye + t d against the box; t0 >= 0. False if it misses.
+// Bounding sphere about the origin (section "Ray-Marching"): narrows [tn, tf] to the
+// roots -b -+ sqrt(b^2 - (|eye|^2 - r^2)) of |eye + t d|^2 = r^2, b = eye.d; false when
+// the ray misses the sphere or the intervals do not meet. cull_r2 = 0: no sphere.
+// P_T is the FP32 or the FP64 record.
+template <typename P_T, typename T>
+__device__ __forceinline__ bool clip_sphere(const P_T &P, const T d[3], T &tn, T &tf) {
+  if (!(P.cull_r2 > 0)) return true;
+  const T ex = T(P.eye[0]), ey = T(P.eye[1]), ez = T(P.eye[2]);
+  const T b = ex * d[0] + ey * d[1] + ez * d[2];
+  const T q = b * b - ((ex * ex + ey * ey + ez * ez) - T(P.cull_r2));
+  if (q < T(0)) return false;
+  const T sq = sqrt(q);
+  const T sa = -b - sq, sb = -b + sq;
+  tn = sa > tn ? sa : tn;
+  tf = sb < tf ? sb : tf;
+  return !(tn > tf);
+}
+
+// x^s for 0 < x <= 1 as exp2(s log2 x) on the hardware transcendental units: relative
+// error a few ulp times s |log2 x|, far inside a shade quantum (shades are stored in
+// FP32 and judged to 1/255). The FP64 path takes it in FP32 too: an FP64 pow would
+// raise that kernel's register count by a quarter for one term of the shade.
+__device__ __forceinline__ float spec_pow(float x, float s) {
+  return __builtin_amdgcn_exp2f(s * __builtin_amdgcn_logf(x));
+}
+__device__ __forceinline__ double spec_pow(double x, double s) {
+  return (double)spec_pow((float)x, (float)s);
+}
+
+// Eq. phong with one directional light of unit intensity: k_a + k_d max(0, n.l), plus
+// k_s max(0, r.v)^s with r = 2 n (n.l) - l and v = -d where the light reaches the surface
+// (n.l > 0); clamped to [0, 1]. P_T is the FP32 or the FP64 record.
+template <typename P_T, typename T>
+__device__ __forceinline__ T phong_shade(const P_T &P, const T n[3], const T d[3]) {
+  const T l0 = T(P.light[0]), l1 = T(P.light[1]), l2 = T(P.light[2]);
+  const T ndl = n[0] * l0 + n[1] * l1 + n[2] * l2;
+  T s = T(P.ka) + T(P.kd) * (ndl > T(0) ? ndl : T(0));
+  if (P.ks > 0 && ndl > T(0)) {
+    const T tn = ndl + ndl;
+    const T rv = (n[0] * tn - l0) * (-d[0]) + (n[1] * tn - l1) * (-d[1]) + (n[2] * tn - l2) * (-d[2]);
+    if (rv > T(0)) s = s + T(P.ks) * spec_pow(rv < T(1) ? rv : T(1), T(P.shininess));
+  }
+  return s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
+}
+
+// Slab clip of the ray eye + t d against the box (and the bounding sphere, if any);
+// t0 >= 0. False if it misses.
 template <typename T>
 __device__ __forceinline__ bool clip_box(const KParams &P, const T d[3], T &t0, T &t1) {
   T tn = T(0), tf = T(INFINITY);
@@ -216,6 +262,7 @@ __device__ __forceinline__ bool clip_box(const KParams &P, const T d[3], T &t0, 
     tf = tb < tf ? tb : tf;
   }
   if (tn > tf) return false;
+  if (!clip_sphere(P, d, tn, tf)) return false;
   t0 = tn;
   t1 = tf;
   return true;
@@ -261,7 +308,7 @@ __device__ __forceinline__ PixelOut miss_pixel(uint8_t flags) {
 }
 
 // Unit normal from the central-difference gradient g; -d when g is zero or not
-// finite. Shade = clamp(k_a + k_d max(0, n.l), 0, 1).
+// finite. Shade: phong_shade.
 template <typename T>
 __device__ __forceinline__ void finish_hit(const KParams &P, const T g[3], const T d[3], T thit,
                                            int kstar, uint8_t flags, PixelOut &r) {
@@ -277,10 +324,7 @@ __device__ __forceinline__ void finish_hit(const KParams &P, const T g[3], const
     n[2] = -d[2];
     flags |= DQJ_FLAG_FALLBACK;
   }
-  T ndl = n[0] * T(P.light[0]) + n[1] * T(P.light[1]) + n[2] * T(P.light[2]);
-  ndl = ndl > T(0) ? ndl : T(0);
-  T s = T(P.ka) + T(P.kd) * ndl;
-  s = s < T(0) ? T(0) : (s > T(1) ? T(1) : s);
+  const T s = phong_shade(P, n, d);
   r.depth = (float)thit;
   r.shade = (float)s;
   r.nx = (float)n[0];

@@ -40,7 +40,12 @@ struct alignas(16) KParams {
   float de_min_step, de_max_step;
   float de_inv_r2;       // 1 / R^2 (the scaled derivative norm, see render_de.hip)
   float de_log2_4r2;     // log2(4 R^2)
-  int32_t pad2[2];
+  int32_t algebra;       // 0: a^2 + (ab + ba) e, 1: a^2 + b^2 e (grid classification only)
+  int32_t normal_mode;   // 0: potential gradient, 1: from the four neighbouring pixels' hits
+  float ks;              // specular coefficient (0: none)
+  float shininess;       // specular exponent
+  float cull_r2;         // bounding sphere radius squared (0: none)
+  int32_t pad2[3];
 };
 static_assert(sizeof(KParams) % 16 == 0, "KParams must be 16-byte sized");
 
@@ -54,6 +59,8 @@ struct alignas(16) KParams64 {
   double light[3];
   double sx_scale, sy_scale, inv_w, inv_h;
   double R2, h, ka, kd;
+  double ks, shininess, cull_r2;
+  int32_t normal_mode, pad;
 };
 
 // What one frame writes (device pointers; optional ones may be null).

@@ -19,6 +19,9 @@ hipError_t launch_render_direct(const KParams &P, const KOut &out, hipStream_t s
 // Distance-estimate march in FP32: one thread per pixel.
 hipError_t launch_render_de(const KParams &P, const KOut &out, hipStream_t s);
 
+// Four-neighbour normal and shade of every hit pixel of a rendered frame, from its depths.
+hipError_t launch_neighbour_normal(const KParams &P, const KOut &out, hipStream_t s);
+
 // Classify n points of R^8 (row-major n x 8) in FP32 / FP64.
 hipError_t launch_classify_f32(const float *pts, int n, const KParams &P, int32_t *esc,
                                float *n2, hipStream_t s);

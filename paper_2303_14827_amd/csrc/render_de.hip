@@ -153,7 +153,9 @@ __device__ void render_pixel_de(const KParams &P, const float *cv, int i, int j,
   }
   const float ph[3] = {fmaf(thit, d[0], P.eye[0]), fmaf(thit, d[1], P.eye[1]),
                        fmaf(thit, d[2], P.eye[2])};
-  float g[3];
+  float g[3] = {0.0f, 0.0f, 0.0f};
+  // (the four-neighbour normal is formed after the frame: no stencil here)
+  if (P.normal_mode == 0)
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float gp = 0.0f;
@@ -367,19 +369,20 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
         else
           gz += sg;
         ++sidx;
-        if (sidx == 6) {
-          const float g[3] = {gx, gy, gz};
-          const float d[3] = {dx, dy, dz};
-          PixelOut r;
-          finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
-          write_pixel(F->out, pix, r);
-          phase = DE_IDLE;
-        }
       }
       if (next_normal) {
         phase = DE_NORMAL;
-        sidx = 0;
+        // the four-neighbour normal is formed after the frame: no stencil points
+        sidx = P.normal_mode != 0 ? 6 : 0;
         gx = gy = gz = 0.0f;
+      }
+      if (phase == DE_NORMAL && sidx == 6) {   // the hit is finished (g = 0: no stencil)
+        const float g[3] = {gx, gy, gz};
+        const float d[3] = {dx, dy, dz};
+        PixelOut r;
+        finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+        write_pixel(F->out, pix, r);
+        phase = DE_IDLE;
       }
       float px = 0, py = 0, pz = 0;
       if (restart) {

@@ -63,7 +63,9 @@ __device__ void render_pixel_f32(const KParams &P, int i, int j, PixelOut &r,
   }
   const float ph[3] = {fmaf(thit, d[0], P.eye[0]), fmaf(thit, d[1], P.eye[1]),
                        fmaf(thit, d[2], P.eye[2])};
-  float g[3];
+  float g[3] = {0.0f, 0.0f, 0.0f};
+  // (the four-neighbour normal is formed after the frame: no stencil here)
+  if (P.normal_mode == 0)
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float gp = 0.0f;

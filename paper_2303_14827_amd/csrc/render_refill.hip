@@ -54,12 +54,11 @@ __device__ __forceinline__ void start_point(const KParams &P, float x, float y, 
 // guarantees that a march sample escaping on its first update escapes on the second,
 // so that update is not tested; only used with AXIS and without COUNT).
 template <int NORM, bool AXIS, bool BATCH, bool COUNT, bool STICKY>
-__global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
-                                                             const FrameDesc *__restrict__ table,
-                                                             const LaunchHeader *__restrict__ hdr,
-                                                             int nframes, uint32_t total_tiles,
-                                                             uint32_t *__restrict__ counter,
-                                                             int TW, int TH) {
+__device__ __forceinline__ void refill_body(const FrameDesc &single,
+                                            const FrameDesc *__restrict__ table,
+                                            const LaunchHeader *__restrict__ hdr, int nframes,
+                                            uint32_t total_tiles, uint32_t *__restrict__ counter,
+                                            int TW, int TH) {
   static_assert(!STICKY || (AXIS && !COUNT), "STICKY needs AXIS and no counting");
   const int lane = lane_id();
   const int tile_rays = TW * TH;
@@ -198,19 +197,20 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
         else
           gz += sg;
         ++sidx;
-        if (sidx == 6) {
-          const float g[3] = {gx, gy, gz};
-          const float d[3] = {dx, dy, dz};
-          PixelOut r;
-          finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
-          write_pixel(F->out, pix, r);
-          phase = PH_IDLE;
-        }
       }
       if (next_normal) {
         phase = PH_NORMAL;
-        sidx = 0;
+        // the four-neighbour normal is formed after the frame: no stencil points
+        sidx = P.normal_mode != 0 ? 6 : 0;
         gx = gy = gz = 0.0f;
+      }
+      if (phase == PH_NORMAL && sidx == 6) {   // the hit is finished (g = 0: no stencil)
+        const float g[3] = {gx, gy, gz};
+        const float d[3] = {dx, dy, dz};
+        PixelOut r;
+        finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+        write_pixel(F->out, pix, r);
+        phase = PH_IDLE;
       }
       float px = 0, py = 0, pz = 0;
       if (restart) {
@@ -362,6 +362,30 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
   if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
 }
 
+// Single-frame launches: the frame record is a kernel argument.
+template <int NORM, bool AXIS, bool COUNT, bool STICKY>
+__global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
+                                                             const FrameDesc *__restrict__ table,
+                                                             const LaunchHeader *__restrict__ hdr,
+                                                             int nframes, uint32_t total_tiles,
+                                                             uint32_t *__restrict__ counter,
+                                                             int TW, int TH) {
+  refill_body<NORM, AXIS, false, COUNT, STICKY>(single, table, hdr, nframes, total_tiles, counter,
+                                                TW, TH);
+}
+
+// Batched launches (frames from a device table: the throughput path) are held to 8 waves
+// per SIMD. Their allocation then fits 64 VGPRs without spilling; left free, rare code
+// of the slow path and the ray set-up pushes it to 65-69 and the occupancy to 7.
+template <int NORM, bool AXIS, bool COUNT, bool STICKY>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void
+render_refill_batch_kernel(FrameDesc single, const FrameDesc *__restrict__ table,
+                           const LaunchHeader *__restrict__ hdr, int nframes,
+                           uint32_t total_tiles, uint32_t *__restrict__ counter, int TW, int TH) {
+  refill_body<NORM, AXIS, true, COUNT, STICKY>(single, table, hdr, nframes, total_tiles, counter,
+                                               TW, TH);
+}
+
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
 template <bool BATCH, bool COUNT>
@@ -369,10 +393,17 @@ static void launch_refill_variant(const FrameDesc &single, const FrameDesc *tabl
                                   const LaunchHeader *hdr, int nframes,
                                   uint32_t total_tiles, int norm, int mode, uint32_t *counter,
                                   const Sched &s, int blocks, int threads, hipStream_t stream) {
-#define DQJ_LAUNCH(NM, AX, ST)                                                                   \
-  hipLaunchKernelGGL((render_refill_kernel<NM, AX, BATCH, COUNT, ST>), dim3(blocks),             \
-                     dim3(threads), 0, stream, single, table, hdr, nframes, total_tiles, counter, \
-                     s.tile_w, s.tile_h)
+#define DQJ_LAUNCH(NM, AX, ST)                                                                 \
+  do {                                                                                         \
+    if constexpr (BATCH)                                                                       \
+      hipLaunchKernelGGL((render_refill_batch_kernel<NM, AX, COUNT, ST>), dim3(blocks),        \
+                         dim3(threads), 0, stream, single, table, hdr, nframes, total_tiles,   \
+                         counter, s.tile_w, s.tile_h);                                         \
+    else                                                                                       \
+      hipLaunchKernelGGL((render_refill_kernel<NM, AX, COUNT, ST>), dim3(blocks), dim3(threads), \
+                         0, stream, single, table, hdr, nframes, total_tiles, counter,         \
+                         s.tile_w, s.tile_h);                                                  \
+  } while (0)
   // counting launches test every first update, so they never take the STICKY variant
   if (COUNT && mode == kSliceIdentitySticky) mode = kSliceIdentity;
   if (norm == 0) {

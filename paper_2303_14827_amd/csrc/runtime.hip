@@ -133,6 +133,16 @@ dqj_status validate_params(const dqj_params *p) {
       return fail(DQJ_E_INVALID,
                   "DE march needs de_hit_eps > 0 and 0 < de_min_step <= de_max_step, finite");
   }
+  if (p->algebra != DQJ_ALGEBRA_DUAL && p->algebra != DQJ_ALGEBRA_COMPONENTWISE)
+    return fail(DQJ_E_INVALID, "algebra must be one of DQJ_ALGEBRA_*");
+  if (p->normal_mode != DQJ_NORMAL_POTENTIAL && p->normal_mode != DQJ_NORMAL_NEIGHBOUR4)
+    return fail(DQJ_E_INVALID, "normal_mode must be one of DQJ_NORMAL_*");
+  if (!fin(p->k_specular) || !(p->k_specular >= 0.0))
+    return fail(DQJ_E_INVALID, "k_specular must be finite and >= 0");
+  if (!fin(p->shininess) || !(p->shininess >= 1.0) || !(p->shininess <= 1e4))
+    return fail(DQJ_E_INVALID, "shininess must be in [1, 1e4]");
+  if (!fin(p->cull_radius) || !(p->cull_radius >= 0.0))
+    return fail(DQJ_E_INVALID, "cull_radius must be finite and >= 0");
   if (p->precision == DQJ_PREC_SPLIT && (p->fp64_window < 1 || p->fp64_window > 8))
     return fail(DQJ_E_INVALID, "fp64_window must be in 1..8 for split precision");
   if (p->precision == DQJ_PREC_SPLIT && !(p->escape_radius * p->escape_radius < 65504.0))
@@ -149,6 +159,14 @@ dqj_status validate_params(const dqj_params *p) {
   const double ll = std::sqrt(p->light_dir[0] * p->light_dir[0] + p->light_dir[1] * p->light_dir[1] +
                               p->light_dir[2] * p->light_dir[2]);
   if (!(ll > 0)) return fail(DQJ_E_INVALID, "light_dir is zero");
+  return DQJ_OK;
+}
+
+dqj_status check_render_modes(const dqj_params &p, bool single) {
+  if (p.algebra != DQJ_ALGEBRA_DUAL)
+    return fail(DQJ_E_UNSUPPORTED, "the component-wise algebra is offered by dqj_classify_grid only");
+  if (p.normal_mode == DQJ_NORMAL_NEIGHBOUR4 && !single)
+    return fail(DQJ_E_UNSUPPORTED, "the four-neighbour normal is offered by dqj_render only");
   return DQJ_OK;
 }
 
@@ -223,6 +241,11 @@ void pack_params(const dqj_params &p, KParams &k) {
   k.de_max_step = (float)p.de_max_step;
   k.de_inv_r2 = (float)(1.0 / (p.escape_radius * p.escape_radius));
   k.de_log2_4r2 = (float)std::log2(4.0 * p.escape_radius * p.escape_radius);
+  k.algebra = p.algebra;
+  k.normal_mode = p.normal_mode;
+  k.ks = (float)p.k_specular;
+  k.shininess = (float)p.shininess;
+  k.cull_r2 = (float)(p.cull_radius * p.cull_radius);
   // On the identity slice zeta_0 = (x, y, z, 0 | 0), so zeta_1 = (a | c_d) with a real
   // quaternion a. If zeta_1 escapes, |a|^2 > R^2 - |c_d|^2 (8 squares) or > R^2 (real
   // part). The real part of zeta_2 is a^2 + c_r and the quaternion norm is
@@ -280,6 +303,10 @@ void pack_params64(const dqj_params &p, KParams64 &k) {
   k.h = p.normal_h;
   k.ka = p.k_ambient;
   k.kd = p.k_diffuse;
+  k.ks = p.k_specular;
+  k.shininess = p.shininess;
+  k.cull_r2 = p.cull_radius * p.cull_radius;
+  k.normal_mode = p.normal_mode;
 }
 
 KOut to_kout(const dqj_frame_out &o) {
@@ -409,6 +436,8 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
                               const dqj_schedule *sched, hipStream_t stream) {
   dqj_status s = validate_params(params);
   if (s != DQJ_OK) return s;
+  s = check_render_modes(*params, true);
+  if (s != DQJ_OK) return s;
   s = validate_out(out);
   if (s != DQJ_OK) return s;
   s = check_schedule(sched);
@@ -440,6 +469,7 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
       e = stream_counter(stream, &counter);
       if (e == hipSuccess) e = launch_render_de_refill(f, counter, sc, cus, stream);
     }
+    if (e == hipSuccess && kp.normal_mode != 0) e = launch_neighbour_normal(kp, ko, stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return DQJ_OK;
   }
@@ -467,6 +497,7 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
       return fail(DQJ_E_UNSUPPORTED, "precision %d is not offered by dqj_render",
                   params->precision);
   }
+  if (e == hipSuccess && kp.normal_mode != 0) e = launch_neighbour_normal(kp, ko, stream);
   if (e != hipSuccess) return hip_fail(e, "render launch");
   return DQJ_OK;
 }
@@ -501,6 +532,8 @@ dqj_status dqj_classify_points(const void *pts_dev, int32_t n, int32_t precision
   DQJ_GUARD({
     dqj_status s = validate_params(params);
     if (s != DQJ_OK) return s;
+    if (params->algebra != DQJ_ALGEBRA_DUAL)
+      return fail(DQJ_E_UNSUPPORTED, "the component-wise algebra is offered by dqj_classify_grid only");
     if (n < 0) return fail(DQJ_E_INVALID, "n must be >= 0");
     if (n > 0 && (!pts_dev || !escape_iter_dev))
       return fail(DQJ_E_INVALID, "points and escape_iter are required");

@@ -12,6 +12,10 @@ dqj_status hip_fail(hipError_t e, const char *what);
 dqj_status current_device(int *dev, int *cus);
 dqj_status validate_params(const dqj_params *p);
 dqj_status validate_out(const dqj_frame_out *o);
+// Modes a render path offers: the component-wise algebra belongs to grid classification
+// only; the four-neighbour normal needs the whole frame's depth, so it is offered by
+// single-frame renders (single = true) only.
+dqj_status check_render_modes(const dqj_params &p, bool single);
 void pack_params(const dqj_params &p, KParams &k);
 void pack_params64(const dqj_params &p, KParams64 &k);
 KOut to_kout(const dqj_frame_out &o);

@@ -297,6 +297,8 @@ dqj_status dqj_serve_submit(dqj_server *s, const dqj_params *params, const dqj_f
   if (!s || !ticket) return fail(DQJ_E_INVALID, "server and ticket are required");
   dqj_status st = validate_params(params);
   if (st != DQJ_OK) return st;
+  st = check_render_modes(*params, false);
+  if (st != DQJ_OK) return st;
   st = validate_out(out);
   if (st != DQJ_OK) return st;
   if (params->precision != s->precision)

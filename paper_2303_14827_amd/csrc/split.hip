@@ -123,6 +123,7 @@ __device__ __forceinline__ bool clip_box64(const KParams64 &P, const double d[3]
     tf = tb < tf ? tb : tf;
   }
   if (tn > tf) return false;
+  if (!clip_sphere(P, d, tn, tf)) return false;
   t0 = tn;
   t1 = tf;
   return true;
@@ -172,8 +173,9 @@ __device__ __forceinline__ uint32_t finish_ray(const P_T &P, const T *c, int N, 
     }
     thit = T(0.5) * (lo + hi);
   }
-  T g[3];
-  for (int a = 0; a < 3; ++a) {
+  T g[3] = {T(0), T(0), T(0)};
+  // (the four-neighbour normal is formed after the frame: no stencil here)
+  for (int a = 0; a < 3 && P.normal_mode == 0; ++a) {
     T gp = T(0);
     for (int sg = 0; sg < 2; ++sg) {
       const T hs = sg == 0 ? h : -h;
@@ -200,10 +202,7 @@ __device__ __forceinline__ uint32_t finish_ray(const P_T &P, const T *c, int N, 
     n[2] = -d[2];
     flags |= DQJ_FLAG_FALLBACK;
   }
-  T ndl = n[0] * T(P.light[0]) + n[1] * T(P.light[1]) + n[2] * T(P.light[2]);
-  ndl = ndl > T(0) ? ndl : T(0);
-  T sh = T(P.ka) + T(P.kd) * ndl;
-  sh = sh < T(0) ? T(0) : (sh > T(1) ? T(1) : sh);
+  const T sh = phong_shade(P, n, d);
   r.depth = (float)thit;
   r.shade = (float)sh;
   r.nx = (float)n[0];

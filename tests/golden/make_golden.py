@@ -10,7 +10,11 @@ ialg_de_1024.json: the same for the same three frames marched by distance estima
 (at most 512 steps, hit below 1e-4, steps clamped to [1e-4, 0.25], 10 bisection steps
 when a step lands inside).
 
-Run:  python tests/golden/make_golden.py [plain|de]
+ialg_voxel_1024.json: for the 1024^3 voxel grid (c from seed 0, max_iter 24, identity
+slice), the updates classification runs (escape index, or max_iter inside, summed over
+voxels) and the number of inside voxels.
+
+Run:  python tests/golden/make_golden.py [plain|de|voxel]
 """
 import json
 import os
@@ -24,7 +28,31 @@ import oracle      # noqa: E402
 import workloads   # noqa: E402
 
 
+def voxel():
+    t = time.time()
+    p, (nx, ny, nz) = workloads.voxel_1024()
+    total, inside = 0, 0
+    for k0 in range(0, nz, 64):   # slabs of 64 planes, to bound memory
+        r = oracle.classify_grid(p, nx, ny, nz, voxels=_slab(nx, ny, k0, min(nz, k0 + 64)))
+        total += r["total_iters"]
+        inside += int(r["inside"].sum())
+        print(k0, total, inside, flush=True)
+    out = {"workload": "voxel_1024", "nx": nx, "ny": ny, "nz": nz, "max_iter": p.max_iter,
+           "c": p.c, "total_iters": total, "inside": inside,
+           "generator": "tests/golden/make_golden.py (FP64 oracle)",
+           "oracle_seconds": round(time.time() - t, 1)}
+    with open(os.path.join(HERE, "ialg_voxel_1024.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+def _slab(nx, ny, k0, k1):
+    import numpy as np
+    return np.arange(k0 * nx * ny, k1 * nx * ny, dtype=np.int64)
+
+
 def main(which):
+    if which == "voxel":
+        return voxel()
     frames = []
     t = time.time()
     ps = workloads.plain_1024() if which == "plain" else workloads.de_1024()

@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -194,6 +194,26 @@ def sweep_256(n: int = 4096, first_seed: int = 0) -> List[Params]:
                    march_steps=256, bisect_steps=8) for i in range(n)]
 
 
+def voxel_grid(n: int, c: Optional[Sequence[float]] = None, max_iter: int = 15,
+               algebra: int = ALGEBRA_DUAL) -> Tuple[Params, Tuple[int, int, int]]:
+    """Dense voxel grid over the box [-1.5, 1.5]^3: n^3 voxel centres, identity slice,
+    R = 4. Default constant and max_iter: the paper's high-detail figure (PAPER_C[7],
+    n = 15), whose set fills about 3.6% of the box. Returns (params, (nx, ny, nz))."""
+    return (Params(c=list(c) if c is not None else list(PAPER_C[7]), width=64, height=64,
+                   max_iter=max_iter, march_steps=64, bisect_steps=0, algebra=algebra),
+            (n, n, n))
+
+
+def voxel_100() -> Tuple[Params, Tuple[int, int, int]]:
+    """The paper's larger voxel prototype size, 100^3."""
+    return voxel_grid(100)
+
+
+def voxel_1024() -> Tuple[Params, Tuple[int, int, int]]:
+    """1024^3 voxels (1.07e9) of the high-detail constant: the throughput case."""
+    return voxel_grid(1024)
+
+
 SERVE_SIDES = (128, 256, 512, 1024, 2048)
 
 
@@ -251,6 +271,8 @@ WORKLOADS = {
     "plain_1024": plain_1024,
     "de_128": de_128,
     "de_1024": de_1024,
+    "voxel_100": voxel_100,
+    "voxel_1024": voxel_1024,
     "split_1080p": split_1080p,
     "sweep_256": sweep_256,
 }
