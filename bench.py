@@ -35,31 +35,43 @@ FP32_FMAC_ISSUE_TFLOPS = 113.2
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB device copy;
 # profiles/render_refill_plain_1024.md). It belongs to the kernel sources it was measured
 # on: bench.py reports it only while their hash is unchanged, else null.
-TRAFFIC_RECORD = {
-    "sources_sha256": "33029dc94e3984dd4522e88b8ae34c75a7375b8993e85c2be60dbcaf9603ea51",
-    "fetch_kib": 63.27, "fetch_factor": 2.0,
-    "write_kib": 37549.26, "write_factor": 1.0,
+# HBM bytes per launch of the timed kernels, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
+# each scaled by what the counter reads for a 256 MiB device copy; valid while the hash of
+# the kernel's sources matches (else the bench line reports null).
+TRAFFIC_RECORDS = {
+    "plain": {
+        "sources": ["paper_2303_14827_amd/csrc/render_refill.hip", "paper_2303_14827_amd/csrc/persist.h",
+                    "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
+                    "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
+                    "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
+                    "include/dqj.h"],
+        "sources_sha256": "a35a22427324d3a85e82c8c7ac3221642c76ae8456c50e50981719642a2408b8",
+        "fetch_kib": 63.40, "fetch_factor": 2.0, "write_kib": 37506.27, "write_factor": 1.0,
+    },
+    "voxel": {
+        "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
+                    "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
+                    "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
+                    "include/dqj.h"],
+        "sources_sha256": "baceaab2d3250d7cc32b2649502abf1a84726dd69382c0111639e3bd157866c5",
+        "fetch_kib": 1255.42, "fetch_factor": 2.0, "write_kib": 2764216.25, "write_factor": 1.0,
+    },
 }
-TRAFFIC_SOURCES = ["paper_2303_14827_amd/csrc/render_refill.hip", "paper_2303_14827_amd/csrc/persist.h",
-                   "paper_2303_14827_amd/csrc/dq_device.h",
-                   "paper_2303_14827_amd/csrc/kparams.h", "paper_2303_14827_amd/csrc/launch.h",
-                   "paper_2303_14827_amd/csrc/refill.h", "paper_2303_14827_amd/csrc/runtime_internal.h",
-                   "paper_2303_14827_amd/build.py", "include/dqj.h"]
 
 
-def sources_sha256():
+def sources_sha256(which="plain"):
     import hashlib
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
+    for rel in TRAFFIC_RECORDS[which]["sources"]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(rel.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
-def recorded_traffic():
+def recorded_traffic(which="plain"):
     """Bytes per launch of the timed kernel, or None if its sources changed since."""
-    r = TRAFFIC_RECORD
-    if sources_sha256() != r["sources_sha256"]:
+    r = TRAFFIC_RECORDS[which]
+    if sources_sha256(which) != r["sources_sha256"]:
         return None
     return (r["fetch_kib"] * r["fetch_factor"] + r["write_kib"] * r["write_factor"]) * 1024.0
 
@@ -456,7 +468,8 @@ def bench_voxel(args, dqj, workloads, torch):
         "voxels_per_s": nvox / (ms * 1e-3),
         "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": recorded_traffic("voxel"),
                      "kernel": "classify_grid_kernel", "kernel_ms_per_step": ev_ms,
                      "flops_per_update": FLOPS_PER_UPDATE,
                      "algorithmic_bytes_per_launch": nvox,
