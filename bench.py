@@ -111,8 +111,9 @@ def _pct(xs, q):
 
 
 def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
-    """The request stream replayed against the server (split precision, continuous
-    batching) and against the plain path (one FP32 dqj_render at a time, FIFO).
+    """The request stream replayed against the server (continuous batching; split
+    precision, the stream's own, and FP32) and against the plain path (one FP32 dqj_render
+    at a time, FIFO).
 
     Open loop: requests are submitted at their scheduled (Poisson) arrival times;
     latency = completion seen by the host - scheduled arrival. Closed loop
@@ -124,8 +125,8 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
 
     stream = workloads.serve_stream(duration_s=duration_s, rate_hz=rate_hz)
 
-    def served(arrivals, open_loop):
-        srv = dqj.Server(precision=workloads.PREC_SPLIT, count_iters=True)
+    def served(arrivals, open_loop, precision=workloads.PREC_SPLIT):
+        srv = dqj.Server(precision=precision, count_iters=True)
         pend = q.Queue()
         t0 = time.monotonic() + 0.05
 
@@ -138,8 +139,9 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
                         time.sleep(dt)
                 out = dqj.alloc_outputs(a.params.width, a.params.height, extras=False)
                 cur.synchronize()   # the zeroed work counter must be in place before the server adds to it
-                tk = srv.submit(a.params, out)
-                pend.put((tk, (t0 + a.t) if open_loop else time.monotonic(), out, a.params))
+                p = a.params.replace(precision=precision)
+                tk = srv.submit(p, out)
+                pend.put((tk, (t0 + a.t) if open_loop else time.monotonic(), out, p))
             pend.put(None)
 
         th = threading.Thread(target=submitter)
@@ -195,17 +197,24 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
     res["served"] = {"precision": "split (FP16 march, FP32 bisection, FP64 re-bisection)",
                      "p50_ms": 1e3 * _pct(sl, 0.5), "p99_ms": 1e3 * _pct(sl, 0.99),
                      "max_ms": 1e3 * max(sl), "epochs": sst["epochs"]}
+    fl, fi, fp, fn, fdur, fst = served(stream, True, workloads.PREC_FP32)
+    res["served_fp32"] = {"precision": "FP32 (the plain path's kernels, continuously batched)",
+                          "p50_ms": 1e3 * _pct(fl, 0.5), "p99_ms": 1e3 * _pct(fl, 0.99),
+                          "max_ms": 1e3 * max(fl), "epochs": fst["epochs"]}
     pl, pi, pp, pn, pdur = plain(stream, True)
     res["plain"] = {"precision": "FP32, one request at a time, FIFO",
                     "p50_ms": 1e3 * _pct(pl, 0.5), "p99_ms": 1e3 * _pct(pl, 0.99),
                     "max_ms": 1e3 * max(pl)}
     cap = stream[:capacity_n]
     cl, ci, cp, cn, cdur, _ = served(cap, False)
+    gl, gi, gp, gn, gdur, _ = served(cap, False, workloads.PREC_FP32)
     ql, qi, qp, qn, qdur = plain(cap, False)
     res["capacity"] = {
         "requests": cn,
         "served": {"req_per_s": cn / cdur, "mpix_per_s": cp / cdur / 1e6,
                    "iters_per_s": ci / cdur, "makespan_s": cdur},
+        "served_fp32": {"req_per_s": gn / gdur, "mpix_per_s": gp / gdur / 1e6,
+                        "iters_per_s": gi / gdur, "makespan_s": gdur},
         "plain": {"req_per_s": qn / qdur, "mpix_per_s": qp / qdur / 1e6,
                   "iters_per_s": qi / qdur, "makespan_s": qdur},
         "note": "iters = DQ updates counted on the GPU (split: FP16 march through the first "

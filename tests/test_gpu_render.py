@@ -245,7 +245,11 @@ def test_batch_matches_single_and_graph_replays(dqj):
     import torch
     ps = [workloads.plain_128(s)[0] for s in range(3)]
     ps += [workloads.plain_1024([2])[0].replace(width=200, height=120),
-           workloads.sweep_256(1, first_seed=6)[0]]
+           workloads.sweep_256(1, first_seed=6)[0],
+           # the specular term and the bounding sphere on the batched kernel
+           workloads.plain_128(3)[0].replace(k_specular=0.4, shininess=20.0, cull_radius=1.35)]
+    for p in ps:
+        p.__post_init__()
     singles = [render_np(dqj, p) for p in ps]
     say("batch eager")
     outs = dqj.render_batch(ps, extras=True)
