@@ -371,41 +371,54 @@ def bench_sweep(args, dqj, workloads, torch):
 
 
 def bench_de(args, dqj, workloads, torch):
-    """plain_1024's three frames marched by distance estimates (FP32, one dqj_render per
-    frame on the default one-thread-per-pixel kernel), against the FP64 oracle's count of
-    the updates that march runs (tests/golden/ialg_de_1024.json). Each DE update also
-    carries the derivative norm: 2 more flops than the fixed march's 52. The persistent
-    lane-refill kernel is timed beside it."""
+    """plain_1024's three frames marched by distance estimates (FP32): one graph-replayed
+    launch per step of the one-thread-per-pixel kernel over the three frames, against the
+    FP64 oracle's count of the updates that march runs (tests/golden/ialg_de_1024.json).
+    Each DE update also carries the derivative norm: 2 more flops than the fixed march's
+    52. The per-frame launches of the three DE kernels are timed beside it."""
     ps = workloads.de_1024()
     with open(os.path.join(ROOT, "tests", "golden", "ialg_de_1024.json")) as f:
         ialg = json.load(f)["total_iters"]
     stream = torch.cuda.current_stream()
     outs = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
-    for p, o in zip(ps, outs):
-        dqj.render(p, out=o, stream=stream)
+    count_plan = dqj.BatchPlan(ps, outs)
+    count_plan.launch(stream)
     torch.cuda.synchronize()
     counted = sum(int(o["iters"].item()) for o in outs)
+    count_plan.close()
     timed = [{k: v for k, v in o.items() if k != "iters"} for o in outs]
 
-    def run(schedule, steps, warmup):
+    def run(step, steps, warmup):
         for _ in range(warmup):
-            for p, o in zip(ps, timed):
-                dqj.render(p, out=o, stream=stream, schedule=schedule)
+            step()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
         for _ in range(steps):
-            for p, o in zip(ps, timed):
-                dqj.render(p, out=o, stream=stream, schedule=schedule)
+            step()
         e1.record(stream)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
 
-    refill_ms, refill_ev = run(dqj.make_schedule(kernel=dqj.KERNEL_REFILL),
-                               max(1, args.steps // 4), 2)
-    ms, ev_ms = run(None, args.steps, args.warmup)
+    def per_frame(kernel):
+        sched = dqj.make_schedule(kernel=kernel)
+
+        def step():
+            for p, o in zip(ps, timed):
+                dqj.render(p, out=o, stream=stream, schedule=sched)
+        return step
+
+    others = {}
+    for name, kern in [("render_de_kernel, one dqj_render per frame", dqj.KERNEL_DIRECT),
+                       ("render_de_refill_kernel, one dqj_render per frame", dqj.KERNEL_REFILL),
+                       ("render_de_lockstep_kernel, one dqj_render per frame", dqj.KERNEL_LOCKSTEP)]:
+        oms, oev = run(per_frame(kern), max(1, args.steps // 4), 2)
+        others[name] = {"ms_per_step": oms, "kernel_ms_per_step": oev, "value": ialg / (oms * 1e-3)}
+    plan = dqj.BatchPlan(ps, timed)
+    ms, ev_ms = run(lambda: plan.launch(stream), args.steps, args.warmup)
+    plan.close()
     flops = FLOPS_PER_UPDATE + 2
     achieved = flops * ialg / (ev_ms * 1e-3) / 1e12
     line = {
@@ -414,17 +427,15 @@ def bench_de(args, dqj, workloads, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "de_1024: plain_1024's 3 frames marched by distance estimates "
                                "(at most 512 steps, hit below 1e-4, steps in [1e-4, 0.25], "
-                               "10 bisection steps), one dqj_render per frame",
+                               "10 bisection steps), one graph-replayed launch per step",
                    "frames": 3, "width": 1024, "height": 1024, "max_iter": 24},
         "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "render_de_kernel", "kernel_ms_per_step": ev_ms,
+                     "kernel": "render_de_batch_kernel", "kernel_ms_per_step": ev_ms,
                      "flops_per_update": flops,
                      "frac_of_measured_fmac_issue": achieved / FP32_FMAC_ISSUE_TFLOPS},
-        "refill_kernel": {"kernel": "render_de_refill_kernel", "ms_per_step": refill_ms,
-                          "kernel_ms_per_step": refill_ev,
-                          "value": ialg / (refill_ms * 1e-3)},
+        "other_kernels": others,
         "ialg_per_step": ialg, "ialg_source": "FP64 oracle, tests/golden/ialg_de_1024.json",
         "gpu_counted_iters_per_step": counted,
         "hits_per_frame": [int(o["mask"].sum().item()) for o in outs],

@@ -155,8 +155,11 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
 
 /* Kernel choice for FP32 renders. REFILL: persistent waves whose lanes take the
  * next sample or ray as soon as theirs retires. DIRECT: one thread per pixel, the
- * method's steps in order, no refill (the simple yardstick). */
-enum { DQJ_KERNEL_AUTO = 0, DQJ_KERNEL_REFILL = 1, DQJ_KERNEL_DIRECT = 2 };
+ * method's steps in order, no refill (the simple yardstick). LOCKSTEP (the
+ * distance-estimate march only): persistent waves that classify all lanes' current
+ * points together, then advance each lane's ray by one point and refill finished
+ * lanes with new rays. Batches take REFILL only. */
+enum { DQJ_KERNEL_AUTO = 0, DQJ_KERNEL_REFILL = 1, DQJ_KERNEL_DIRECT = 2, DQJ_KERNEL_LOCKSTEP = 3 };
 
 /* Work schedule of the persistent kernels (chosen by dqj_autotune, or by hand).
  * Any field 0 = library default. A schedule changes speed only: every schedule

@@ -24,7 +24,7 @@ NORMAL_POTENTIAL, NORMAL_NEIGHBOUR4 = 0, 1
 
 NORM_EUCLID8, NORM_REALPART = 0, 1
 PREC_FP32, PREC_SPLIT, PREC_FP64 = 0, 1, 2
-KERNEL_AUTO, KERNEL_REFILL, KERNEL_DIRECT = 0, 1, 2
+KERNEL_AUTO, KERNEL_REFILL, KERNEL_DIRECT, KERNEL_LOCKSTEP = 0, 1, 2, 3
 FLAG_BOX, FLAG_HIT, FLAG_FP64, FLAG_FALLBACK = 1, 2, 4, 8
 
 

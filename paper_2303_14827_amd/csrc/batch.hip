@@ -14,6 +14,7 @@
 
 #include "dqj.h"
 #include "kparams.h"
+#include "launch.h"
 #include "refill.h"
 #include "split.h"
 #include "runtime_internal.h"
@@ -42,8 +43,10 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
     st = validate_out(outs + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
-    if (params[i].march != DQJ_MARCH_FIXED)
-      return fail(DQJ_E_UNSUPPORTED, "frame %d: the distance-estimate march runs through dqj_render", i);
+    if (i > 0 && params[i].march != params[0].march)
+      return fail(DQJ_E_INVALID, "frame %d: all frames of a batch must share the march", i);
+    if (params[i].march == DQJ_MARCH_DE && params[i].precision != DQJ_PREC_FP32)
+      return fail(DQJ_E_UNSUPPORTED, "frame %d: the distance-estimate march runs in FP32 only", i);
     if (params[i].precision != DQJ_PREC_FP32 && params[i].precision != DQJ_PREC_SPLIT)
       return fail(DQJ_E_UNSUPPORTED, "frame %d: batched renders run in FP32 or split precision", i);
     if (i > 0 && params[i].precision != params[0].precision)
@@ -69,6 +72,17 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
   norm = params[0].norm;
   precision = params[0].precision;
   return DQJ_OK;
+}
+
+// A batch of distance-estimate frames: one one-thread-per-pixel launch over the table.
+hipError_t launch_de_table(const FrameDesc *dev, const std::vector<FrameDesc> &table, int norm,
+                           bool all_axis, hipStream_t s) {
+  int mw = 0, mh = 0;
+  for (const FrameDesc &f : table) {
+    mw = f.P.W > mw ? f.P.W : mw;
+    mh = f.P.H > mh ? f.P.H : mh;
+  }
+  return launch_render_de_batch(dev, (int)table.size(), mw, mh, norm, all_axis, s);
 }
 
 // Allocations an eager batch leaves behind until the stream has passed them.
@@ -161,7 +175,9 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
       return fail(DQJ_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
     e = hipMemcpyAsync(r.dev, r.host, bytes, hipMemcpyHostToDevice, stream);
-    if (precision == DQJ_PREC_FP32) {
+    if (table[0].P.march == DQJ_MARCH_DE) {
+      if (e == hipSuccess) e = launch_de_table((const FrameDesc *)r.dev, table, norm, all_axis, stream);
+    } else if (precision == DQJ_PREC_FP32) {
       uint32_t *counter = nullptr;
       if (e == hipSuccess) e = stream_counter(stream, &counter);
       if (e == hipSuccess)
@@ -209,7 +225,7 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
                   sizeof(dqj_schedule));
     if (n < 1 || !params) return fail(DQJ_E_INVALID, "batch size must be >= 1 with params");
     const Sched s = pick_schedule(sched, params[0], cus);
-    if (s.kernel == DQJ_KERNEL_DIRECT)
+    if (s.kernel == DQJ_KERNEL_DIRECT || s.kernel == DQJ_KERNEL_LOCKSTEP)
       return fail(DQJ_E_UNSUPPORTED, "batched renders use the refill kernel");
     std::vector<FrameDesc> table;
     uint32_t total = 0;
@@ -239,7 +255,9 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     if (e == hipSuccess) {
       // The capture holds a counter-reset kernel (not a memset node) and the kernel.
       hipError_t le =
-          precision == DQJ_PREC_FP32
+          table[0].P.march == DQJ_MARCH_DE
+              ? launch_de_table(p->table_dev, table, norm, all_axis, p->cap_stream)
+          : precision == DQJ_PREC_FP32
               ? launch_render_refill_batch(p->table_dev, nullptr, n, total, norm, slice_mode, any_count,
                                            p->counter_dev, s, cus, p->cap_stream)
               : launch_render_split_batch(p->table_dev, nullptr, n, total, norm, all_axis, any_count,

@@ -16,8 +16,14 @@ struct KIter64 {
 // Straightforward FP32 render: one thread per pixel, no lane refill.
 hipError_t launch_render_direct(const KParams &P, const KOut &out, hipStream_t s);
 
-// Distance-estimate march in FP32: one thread per pixel.
-hipError_t launch_render_de(const KParams &P, const KOut &out, hipStream_t s);
+// Distance-estimate march in FP32: one thread per pixel, blocks of waves_per_block (1-4)
+// waves of 16 x 4 pixels each.
+hipError_t launch_render_de(const KParams &P, const KOut &out, int waves_per_block, hipStream_t s);
+
+// The distance-estimate march over n frames of a device table (one-thread-per-pixel kernel,
+// frame = blockIdx.z); all frames share norm; all_axis: every frame on the identity slice.
+hipError_t launch_render_de_batch(const FrameDesc *table_dev, int nframes, int max_w, int max_h,
+                                  int norm, bool all_axis, hipStream_t s);
 
 // Four-neighbour normal and shade of every hit pixel of a rendered frame, from its depths.
 hipError_t launch_neighbour_normal(const KParams &P, const KOut &out, hipStream_t s);

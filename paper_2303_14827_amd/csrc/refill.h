@@ -31,6 +31,8 @@ hipError_t launch_render_refill_batch(const FrameDesc *table_dev, const LaunchHe
 // norm from a device table (all_axis: every frame uses the identity slice).
 hipError_t launch_render_de_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
                                    hipStream_t stream);
+hipError_t launch_render_de_lockstep(const FrameDesc &frame, uint32_t *counter, const Sched &s,
+                                     int cus, hipStream_t stream);
 hipError_t launch_render_de_refill_batch(const FrameDesc *table_dev, const LaunchHeader *hdr_dev,
                                          int nframes, uint32_t total_tiles, int norm, bool all_axis,
                                          bool any_count, uint32_t *counter, const Sched &s, int cus,

@@ -177,10 +177,13 @@ __device__ void render_pixel_de(const KParams &P, const float *cv, int i, int j,
   finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
 }
 
+// Blocks of 16 x (4 waves_per_block) pixels, one wave per 16 x 4 stripe: a block keeps
+// its slot on the CU until its slowest wave is done, and DE work per wave varies widely,
+// so small blocks free slots sooner.
 template <int NORM, bool AXIS>
-__global__ __launch_bounds__(256) void render_de_kernel(KParams P, KOut out) {
+__device__ __forceinline__ void render_de_block(const KParams &P, const KOut &out) {
   const int i = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int j = blockIdx.y * (blockDim.x >> 4) + (threadIdx.x >> 4);
   float cv[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(P.c[q]);
@@ -193,12 +196,31 @@ __global__ __launch_bounds__(256) void render_de_kernel(KParams P, KOut out) {
   if (out.iters) wave_add_u64(out.iters, iters);
 }
 
+template <int NORM, bool AXIS>
+__global__ __launch_bounds__(256) void render_de_kernel(KParams P, KOut out) {
+  render_de_block<NORM, AXIS>(P, out);
+}
+
+// Several frames in one launch (frame = blockIdx.z, records from a device table): the
+// hardware dispatches the frames' blocks in turn, so one frame's slowest waves overlap
+// the next frame's work instead of ending a launch each.
+template <int NORM, bool AXIS>
+__global__ __launch_bounds__(256) void render_de_batch_kernel(const FrameDesc *__restrict__ table) {
+  const persist::ConstFrame F = (persist::ConstFrame)table + blockIdx.z;
+  const KParams &P = F->P;
+  if ((int)(blockIdx.x * 16) >= P.W || (int)(blockIdx.y * (blockDim.x >> 4)) >= P.H) return;
+  render_de_block<NORM, AXIS>(P, F->out);
+}
+
 }  // namespace
 
-hipError_t launch_render_de(const KParams &P, const KOut &out, hipStream_t s) {
-  dim3 grid((P.W + 15) / 16, (P.H + 15) / 16);
+hipError_t launch_render_de(const KParams &P, const KOut &out, int waves_per_block, hipStream_t s) {
+  const int wpb = waves_per_block < 1 ? 1 : (waves_per_block > 4 ? 4 : waves_per_block);
+  const int bh = 4 * wpb;
+  dim3 grid((P.W + 15) / 16, (P.H + bh - 1) / bh);
   const bool axis = P.axis_slice != 0;
-#define DQJ_DE_DIRECT(NM, AX) hipLaunchKernelGGL((render_de_kernel<NM, AX>), grid, dim3(256), 0, s, P, out)
+#define DQJ_DE_DIRECT(NM, AX) \
+  hipLaunchKernelGGL((render_de_kernel<NM, AX>), grid, dim3(64 * wpb), 0, s, P, out)
   if (P.norm == 0) {
     if (axis)
       DQJ_DE_DIRECT(0, true);
@@ -211,6 +233,26 @@ hipError_t launch_render_de(const KParams &P, const KOut &out, hipStream_t s) {
       DQJ_DE_DIRECT(1, false);
   }
 #undef DQJ_DE_DIRECT
+  return hipGetLastError();
+}
+
+hipError_t launch_render_de_batch(const FrameDesc *table_dev, int nframes, int max_w, int max_h,
+                                  int norm, bool all_axis, hipStream_t s) {
+  const dim3 grid((max_w + 15) / 16, (max_h + 3) / 4, nframes);
+#define DQJ_DE_BATCH(NM, AX) \
+  hipLaunchKernelGGL((render_de_batch_kernel<NM, AX>), grid, dim3(64), 0, s, table_dev)
+  if (norm == 0) {
+    if (all_axis)
+      DQJ_DE_BATCH(0, true);
+    else
+      DQJ_DE_BATCH(0, false);
+  } else {
+    if (all_axis)
+      DQJ_DE_BATCH(1, true);
+    else
+      DQJ_DE_BATCH(1, false);
+  }
+#undef DQJ_DE_BATCH
   return hipGetLastError();
 }
 
@@ -491,6 +533,208 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
   if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
 }
 
+// Lock-step persistent form: every lane holds one ray and one current point (a march
+// point, a bisection point or a normal stencil point). Each pass classifies all lanes'
+// points together (the loop runs until the last lane's point escapes or reaches
+// max_iter), then every lane advances its own ray once -- step, bisect, accumulate the
+// normal, or finish -- and lanes whose ray ended take new rays of the wave's tile. The
+// per-point work is paid once per classification, not once per update, and a wave no
+// longer waits for its slowest ray: it waits for its slowest point.
+template <int NORM, bool AXIS, bool COUNT>
+__global__ __launch_bounds__(1024) void render_de_lockstep_kernel(FrameDesc F, uint32_t *__restrict__ counter,
+                                                                  int TW, int TH) {
+  const KParams &P = F.P;
+  const int lane = lane_id();
+  const int tile_rays = TW * TH;
+  float cv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(P.c[q]);
+  const float R2 = P.R2, inv_r2 = P.de_inv_r2, l4r2 = P.de_log2_4r2;
+  const float eps = P.de_eps, smin = P.de_min_step, smax = P.de_max_step;
+  const float ex = P.eye[0], ey = P.eye[1], ez = P.eye[2];
+  const int N = P.N, S = P.S, B = P.B;
+
+  uint32_t tile = 0;
+  int next_r = 0;
+  bool have_tile = false, exhausted = false;
+
+  int phase = DE_IDLE;
+  int pix = 0;
+  float dx = 0, dy = 0, dz = 0, t0 = 0, t1 = 0, t = 0, tprev = 0;
+  float px = 0, py = 0, pz = 0;        // the lane's current point
+  int k = 0, b = 0, sidx = 0, kstar = -1;
+  float lo = 0, hi = 0, thit = 0, gx = 0, gy = 0, gz = 0;
+  unsigned long long it_lane = 0;
+
+  for (;;) {
+    // ---- hand new rays to idle lanes
+    uint64_t idle = __builtin_amdgcn_ballot_w64(phase == DE_IDLE);
+    while (idle) {
+      if (!have_tile) {
+        if (exhausted) break;
+        uint32_t tt = 0;
+        if (lane == 0) tt = atomicAdd(counter, 1u);
+        tt = uniform(tt);
+        if (tt >= F.ntiles) {
+          exhausted = true;
+          break;
+        }
+        tile = tt;
+        next_r = 0;
+        have_tile = true;
+      }
+      const int rank = rank_in(idle);
+      const int avail = tile_rays - next_r;
+      if (phase == DE_IDLE && rank < avail) {
+        const int r = next_r + rank;
+        const int i = (int)(tile % F.tiles_x) * TW + r % TW;
+        const int j = (int)(tile / F.tiles_x) * TH + r / TW;
+        if (i < P.W && j < P.H) {
+          pix = j * P.W + i;
+          float d[3];
+          pixel_dir(P, i, j, d);
+          float ta, tb;
+          if (clip_box(P, d, ta, tb)) {
+            dx = d[0];
+            dy = d[1];
+            dz = d[2];
+            t0 = ta;
+            t1 = tb;
+            t = ta;
+            tprev = ta;
+            k = 0;
+            kstar = -1;
+            phase = DE_MARCH;
+            px = fmaf(t, dx, ex);
+            py = fmaf(t, dy, ey);
+            pz = fmaf(t, dz, ez);
+          } else {
+            write_pixel(F.out, pix, miss_pixel(0));
+          }
+        }
+      }
+      const int cnt = __popcll(idle);
+      next_r += cnt < avail ? cnt : avail;
+      if (next_r >= tile_rays) have_tile = false;
+      idle = __builtin_amdgcn_ballot_w64(phase == DE_IDLE);
+    }
+    if (exhausted && !__builtin_amdgcn_ballot_w64(phase != DE_IDLE)) break;
+
+    // ---- classify every busy lane's point together
+    float n2 = 0.0f, D = 1.0f;
+    int m = N;
+    bool inside = true;
+    if (phase != DE_IDLE) {
+      DQ<float> z;
+      float sv;
+      de_start<AXIS>(P, px, py, pz, z, sv);
+      n2 = norm2_of<NORM>(z, sv);
+      int n = 0;
+      while (n < N) {
+        ++n;
+        D = D * (n2 * inv_r2);
+        n2 = de_update<NORM>(z, sv, cv);
+        if (n2 > R2) {
+          inside = false;
+          break;
+        }
+      }
+      m = inside ? N : n;
+      if (COUNT) it_lane += (unsigned long long)m;
+    }
+
+    // ---- advance each lane's ray by one point
+    bool next_normal = false;
+    if (phase == DE_MARCH) {
+      if (inside) {               // the step landed inside: bisect it (or hit at t0)
+        kstar = k;
+        if (k == 0) {
+          thit = t0;
+          next_normal = true;
+        } else if (B == 0) {
+          thit = 0.5f * (tprev + t);
+          next_normal = true;
+        } else {
+          lo = tprev;
+          hi = t;
+          b = 0;
+          phase = DE_BISECT;
+        }
+      } else {
+        const float de = de_estimate(n2, D, m, l4r2);
+        if (de < eps) {           // the estimate fell below the threshold: hit here
+          kstar = k;
+          thit = t;
+          next_normal = true;
+        } else {
+          const float tn = t + fminf(fmaxf(de, smin), smax);
+          if (tn <= t1 && k + 1 < S) {
+            tprev = t;
+            t = tn;
+            ++k;
+            px = fmaf(t, dx, ex);
+            py = fmaf(t, dy, ey);
+            pz = fmaf(t, dz, ez);
+          } else {                // left the box or ran out of steps: miss
+            write_pixel(F.out, pix, miss_pixel(DQJ_FLAG_BOX));
+            phase = DE_IDLE;
+          }
+        }
+      }
+    } else if (phase == DE_BISECT) {
+      const float tm = 0.5f * (lo + hi);
+      if (inside)
+        hi = tm;
+      else
+        lo = tm;
+      ++b;
+      if (b >= B) {
+        thit = 0.5f * (lo + hi);
+        next_normal = true;
+      }
+    } else if (phase == DE_NORMAL) {
+      const float G = potential(n2, m);
+      const float sg = (sidx & 1) ? -G : G;
+      const int axis = sidx >> 1;
+      if (axis == 0)
+        gx += sg;
+      else if (axis == 1)
+        gy += sg;
+      else
+        gz += sg;
+      ++sidx;
+    }
+    if (next_normal) {
+      phase = DE_NORMAL;
+      // the four-neighbour normal is formed after the frame: no stencil points
+      sidx = P.normal_mode != 0 ? 6 : 0;
+      gx = gy = gz = 0.0f;
+    }
+    if (phase == DE_NORMAL && sidx == 6) {   // the hit is finished (g = 0: no stencil)
+      const float g[3] = {gx, gy, gz};
+      const float d[3] = {dx, dy, dz};
+      PixelOut r;
+      finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+      write_pixel(F.out, pix, r);
+      phase = DE_IDLE;
+    }
+    // next point of a bisecting or normal lane
+    if (phase == DE_BISECT) {
+      const float tm = 0.5f * (lo + hi);
+      px = fmaf(tm, dx, ex);
+      py = fmaf(tm, dy, ey);
+      pz = fmaf(tm, dz, ez);
+    } else if (phase == DE_NORMAL) {
+      const int axis = sidx >> 1;
+      const float hs = (sidx & 1) ? -P.h : P.h;
+      px = fmaf(thit, dx, ex) + (axis == 0 ? hs : 0.0f);
+      py = fmaf(thit, dy, ey) + (axis == 1 ? hs : 0.0f);
+      pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
+    }
+  }
+  if (COUNT && F.out.iters) wave_add_u64(F.out.iters, it_lane);
+}
+
 __global__ void de_reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
 template <bool BATCH, bool COUNT>
@@ -530,6 +774,32 @@ static hipError_t launch_de_impl(const FrameDesc &single, const FrameDesc *table
   else
     launch_de_variant<BATCH, false>(single, table, hdr, nframes, total_tiles, norm, axis, counter, s,
                                     blocks, threads, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_de_lockstep(const FrameDesc &frame, uint32_t *counter, const Sched &s,
+                                     int cus, hipStream_t stream) {
+  hipLaunchKernelGGL(de_reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+  const int threads = 64 * s.waves_per_block;
+  const int blocks = cus * s.blocks_per_cu;
+  const bool axis = frame.P.axis_slice != 0, count = frame.out.iters != nullptr;
+#define DQJ_DE_LS(NM, AX, CT)                                                                  \
+  hipLaunchKernelGGL((render_de_lockstep_kernel<NM, AX, CT>), dim3(blocks), dim3(threads), 0, \
+                     stream, frame, counter, s.tile_w, s.tile_h)
+  if (frame.P.norm == 0) {
+    if (axis) {
+      if (count) DQJ_DE_LS(0, true, true); else DQJ_DE_LS(0, true, false);
+    } else {
+      if (count) DQJ_DE_LS(0, false, true); else DQJ_DE_LS(0, false, false);
+    }
+  } else {
+    if (axis) {
+      if (count) DQJ_DE_LS(1, true, true); else DQJ_DE_LS(1, true, false);
+    } else {
+      if (count) DQJ_DE_LS(1, false, true); else DQJ_DE_LS(1, false, false);
+    }
+  }
+#undef DQJ_DE_LS
   return hipGetLastError();
 }
 

@@ -344,7 +344,7 @@ static dqj_status check_schedule(const dqj_schedule *s) {
   if (!s) return DQJ_OK;
   if (s->struct_size != sizeof(dqj_schedule))
     return fail(DQJ_E_INVALID, "schedule.struct_size %u != %zu", s->struct_size, sizeof(dqj_schedule));
-  if (s->kernel < 0 || s->kernel > DQJ_KERNEL_DIRECT)
+  if (s->kernel < 0 || s->kernel > DQJ_KERNEL_LOCKSTEP)
     return fail(DQJ_E_INVALID, "schedule.kernel must be one of DQJ_KERNEL_*");
   if (s->tile_w < 0 || s->tile_h < 0 || s->tile_w * s->tile_h > 4096)
     return fail(DQJ_E_INVALID, "schedule tile must satisfy tile_w * tile_h <= 4096");
@@ -456,8 +456,19 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
     // a few updates, so the refill kernel's per-point estimate and restart run on nearly
     // every trip; the persistent form is taken only when asked for.
     const Sched sc = resolve_schedule(sched, cus);
-    if (!sched || sched->kernel != DQJ_KERNEL_REFILL) {
-      e = launch_render_de(kp, ko, stream);
+    if (sched && sched->kernel == DQJ_KERNEL_LOCKSTEP) {
+      FrameDesc f;
+      memset(&f, 0, sizeof f);
+      f.P = kp;
+      f.out = ko;
+      f.tile_begin = 0;
+      set_tiles(f, sc.tile_w, sc.tile_h);
+      uint32_t *counter = nullptr;
+      e = stream_counter(stream, &counter);
+      if (e == hipSuccess) e = launch_render_de_lockstep(f, counter, sc, cus, stream);
+    } else if (!sched || sched->kernel != DQJ_KERNEL_REFILL) {
+      e = launch_render_de(kp, ko, (sched && sched->waves_per_block) ? sched->waves_per_block : 1,
+                           stream);
     } else {
       FrameDesc f;
       memset(&f, 0, sizeof f);
@@ -473,6 +484,8 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return DQJ_OK;
   }
+  if (sched && sched->kernel == DQJ_KERNEL_LOCKSTEP)
+    return fail(DQJ_E_UNSUPPORTED, "the lock-step kernel runs the distance-estimate march only");
   switch (params->precision) {
     case DQJ_PREC_FP32:
       e = launch_render_fp32(kp, ko, pick_schedule(sched, *params, cus), cus, stream);

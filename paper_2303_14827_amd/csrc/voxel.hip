@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <new>
 
 #include "dq_device.h"
 #include "kparams.h"
@@ -331,6 +332,8 @@ extern "C" dqj_status dqj_classify_grid(const dqj_params *params, int32_t nx, in
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "grid launch");
     return DQJ_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(DQJ_E_NOMEM, "host allocation failed");
   } catch (...) {
     return fail(DQJ_E_DEVICE, "unexpected internal error");
   }

@@ -1,7 +1,7 @@
 """GPU distance-estimate march (FP32) against the FP64 oracle's DE march, and the
-c = 0 closed form: every hit bisected onto the ball of radius R^(2^-N). Both kernels
-run: the one-thread-per-pixel kernel (the default for this march) and the persistent
-lane-refill kernel (KERNEL_REFILL).
+c = 0 closed form: every hit bisected onto the ball of radius R^(2^-N). Every kernel
+runs: the one-thread-per-pixel kernel (KERNEL_DIRECT), the persistent lane-refill kernel
+(KERNEL_REFILL) and the persistent point-lock-step kernel (KERNEL_LOCKSTEP).
 
 Mask and depth meet the plain path's bar. Shading is held to 99% of agreeing hits
 within 1/255 (DE_SHADE_FRAC): a DE hit is where a chaotic estimate first drops below the
@@ -33,11 +33,12 @@ def dqj():
     return m
 
 
-KERNELS = ["refill", "direct"]
+KERNELS = ["refill", "direct", "lockstep"]
 
 
 def sched(dqj, kernel):
-    k = dqj.KERNEL_REFILL if kernel == "refill" else dqj.KERNEL_DIRECT
+    k = {"refill": dqj.KERNEL_REFILL, "direct": dqj.KERNEL_DIRECT,
+         "lockstep": dqj.KERNEL_LOCKSTEP}[kernel]
     return dqj.make_schedule(kernel=k)
 
 
@@ -119,7 +120,7 @@ def test_de_paper_constant_and_eye_inside_box(dqj, kernel):
 @pytest.mark.parametrize("case", ["ragged_131x97", "tiny_1x1", "S1", "N1", "B0", "dual_slice",
                                   "steps_clamped_small"])
 def test_de_edge_cases(dqj, case, kernel):
-    """Degenerate sizes and parameters of the DE march on both kernels: a ragged
+    """Degenerate sizes and parameters of the DE march on every kernel: a ragged
     frame over several tiles, one pixel, one march step, one update (every estimate is
     that of z_1), no bisection, a slice through the dual part, and a step range so
     narrow that rays run out of steps inside the box."""
@@ -150,6 +151,38 @@ def test_de_edge_cases(dqj, case, kernel):
     assert_parity(rep, 0.999, DE_SHADE_FRAC)
 
 
+def test_de_batch_matches_single(dqj):
+    """A batch of DE frames (one launch over a frame table, also graph-captured) gives the
+    single renders' results bit for bit."""
+    import torch
+    ps = [workloads.de_128()[0], workloads.de_128()[0].replace(c=workloads.PAPER_C[7], max_iter=15),
+          workloads.de_128()[0].replace(width=97, height=61, norm=workloads.NORM_REALPART)]
+    for p in ps:
+        p.__post_init__()
+    ps = ps[:2]   # one norm per batch
+    singles = [render(dqj, p) for p in ps]
+    outs = dqj.render_batch(ps, extras=True)
+    torch.cuda.synchronize()
+    for o, g in zip(outs, singles):
+        o = to_numpy(o)
+        for k in ("mask", "depth", "shade", "normal", "first_hit", "iters"):
+            np.testing.assert_array_equal(o[k], g[k], err_msg=k)
+    outs2 = [dqj.alloc_outputs(p.width, p.height) for p in ps]
+    plan = dqj.BatchPlan(ps, outs2)
+    for rep in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        for o, g in zip(outs2, singles):
+            o = to_numpy(o)
+            for k in ("mask", "depth", "shade"):
+                np.testing.assert_array_equal(o[k], g[k], err_msg=f"replay {rep} {k}")
+        if rep < 2:
+            for o in outs2:
+                o["mask"].zero_()
+                o["depth"].zero_()
+    plan.close()
+
+
 def test_de_modes_not_offered(dqj):
     import ctypes
     p = workloads.de_128()[0]
@@ -157,8 +190,17 @@ def test_de_modes_not_offered(dqj):
     fo = dqj.make_frame_out(dqj.alloc_outputs(128, 128))
     st = dqj.lib().dqj_render(ctypes.byref(sp), ctypes.byref(fo), None)
     assert st == dqj.E_UNSUPPORTED
+    # a batch shares one march; DE batches are FP32
     with pytest.raises(Exception):
-        dqj.render_batch([p, p])
+        dqj.render_batch([p, workloads.plain_128()[0]])
+    with pytest.raises(Exception):
+        dqj.render_batch([p.replace(precision=workloads.PREC_SPLIT)] * 2)
+    # the lock-step kernel runs the DE march only
+    fixed = workloads.plain_128()[0]
+    st = dqj.lib().dqj_render_scheduled(ctypes.byref(dqj.make_params(fixed)), ctypes.byref(fo),
+                                        ctypes.byref(dqj.make_schedule(kernel=dqj.KERNEL_LOCKSTEP)),
+                                        None)
+    assert st == dqj.E_UNSUPPORTED
     with dqj.Server(precision=workloads.PREC_FP32) as srv:
         st, _ = srv.submit_status(p, dqj.alloc_outputs(128, 128, extras=False))
         assert st == dqj.E_UNSUPPORTED

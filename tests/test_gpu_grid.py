@@ -180,3 +180,9 @@ def test_grid_rejections(dqj):
     # the smallest grid
     g = gpu_grid(dqj, p, 1, 1, 1)
     assert g["mask"].shape == (1, 1, 1)
+
+
+def test_grid_paper_size_100(dqj):
+    """The paper's larger voxel prototype, 100^3, in full."""
+    p, dims = workloads.voxel_100()
+    check_against_oracle(dqj, p, dims)

@@ -126,3 +126,25 @@ def test_neighbour_normal_not_in_batches(dqj):
     p = workloads.plain_128()[0].replace(width=32, height=32, normal_mode=workloads.NORMAL_NEIGHBOUR4)
     with pytest.raises(Exception):
         dqj.render_batch([p, p])
+
+
+def test_animated_slices_batch(dqj):
+    """An animated slice turning from the real k axis into the dual scalar axis: the batch
+    render of the sequence equals the single renders bitwise, and the first, middle and
+    last frames meet the parity bar against the oracle."""
+    import oracle
+    import torch
+    ps = workloads.animated_slices(n=9, side=96)
+    singles = [render(dqj, p, "refill") for p in ps]
+    outs = dqj.render_batch(ps, extras=True)
+    torch.cuda.synchronize()
+    for o, g in zip(outs, singles):
+        o = to_numpy(o)
+        for k in ("mask", "depth", "shade", "normal", "first_hit"):
+            np.testing.assert_array_equal(o[k], g[k], err_msg=k)
+    for f in (0, 4, 8):
+        rep = compare(ps[f], singles[f], oracle.render(ps[f]))
+        say("frame", f, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+        assert_parity(rep, *BARS["refill"])
+    # the slice really changes the image
+    assert not np.array_equal(singles[0]["mask"], singles[8]["mask"])

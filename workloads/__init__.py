@@ -214,6 +214,23 @@ def voxel_1024() -> Tuple[Params, Tuple[int, int, int]]:
     return voxel_grid(1024)
 
 
+def animated_slices(n: int = 16, side: int = 256) -> List[Params]:
+    """An animated slice (section "Dimension Reduction"): n frames of the paper's
+    high-detail constant (PAPER_C[7], n = 15) whose third slice axis turns from the real
+    k axis into the dual part's scalar axis, W = cos(theta) e2 + sin(theta) e4 with
+    theta = f/(n-1) * pi/2, so the last frame slices (X, Y, d0). Each frame is an ordinary
+    render; a batch renders the sequence."""
+    out: List[Params] = []
+    for f in range(n):
+        th = 0.5 * math.pi * f / max(n - 1, 1)
+        w = [0.0] * 8
+        w[2], w[4] = math.cos(th), math.sin(th)
+        axes = [[1.0, 0, 0, 0, 0, 0, 0, 0], [0, 1.0, 0, 0, 0, 0, 0, 0], w]
+        out.append(Params(c=list(PAPER_C[7]), width=side, height=side, max_iter=15,
+                          march_steps=256, bisect_steps=8, slice_axes=axes))
+    return out
+
+
 SERVE_SIDES = (128, 256, 512, 1024, 2048)
 
 
