@@ -33,17 +33,121 @@ namespace {
 
 enum { PH_IDLE = 0, PH_MARCH = 1, PH_BISECT = 2, PH_NORMAL = 3 };
 
-// zeta_0 for a world point and |a_v|^2 of it.
+// ---- the update in "q form"
+// The loop carries q = c0 - |a_v|^2 beside zeta, so the new real part is one FMA,
+// a0' = a0^2 + q, and tests ||zeta'||^2 - c0 = a0'^2 - q' + |b'|^2 (NORM 0; NORM 1
+// drops the |b'|^2) against R^2 - c0. Every other term of the square (Eq. quatsq and
+// the dual part, whose cross products cancel) carries a factor 2. With the Julia
+// constant halved (h_i = c_i / 2, i >= 1) that factor is the FMA's x2 output modifier:
+// round(x) * 2 = round(2 x) exactly, so the result is the same as forming 2 a0 and
+// 2 b0 first, without those two operations. 22 VALU operations per update.
+//
+// The output modifier takes effect only with the IEEE mode bit clear and FP32
+// output denormals flushed; enter_update_mode() sets both for the calling wave. The
+// march never depends on denormal values (they are far below every escape radius
+// and step), and no signalling NaN enters the kernel.
+__device__ __forceinline__ void enter_update_mode() {
+  asm volatile(
+      "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 9, 1), 0\n\t"   // IEEE mode off
+      "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 4, 2), 0\n\t"   // FP32 denormals flushed
+      "s_nop 3" ::: "memory");
+}
+
+__device__ __forceinline__ float dq_update_q_asm(DQ<float> &z, float &q, const float *h) {
+  float d, n;
+  asm("s_nop 1\n\t"
+      "v_fma_f32 %[d], -%[a3], %[b3], %[h4]\n\t"
+      "v_fma_f32 %[d], -%[a2], %[b2], %[d]\n\t"
+      "v_fma_f32 %[d], -%[a1], %[b1], %[d]\n\t"
+      "v_fma_f32 %[b1], %[a0], %[b1], %[h5]\n\t"
+      "v_fma_f32 %[b1], %[b0], %[a1], %[b1] mul:2\n\t"
+      "v_fma_f32 %[b2], %[a0], %[b2], %[h6]\n\t"
+      "v_fma_f32 %[b2], %[b0], %[a2], %[b2] mul:2\n\t"
+      "v_fma_f32 %[b3], %[a0], %[b3], %[h7]\n\t"
+      "v_fma_f32 %[b3], %[b0], %[a3], %[b3] mul:2\n\t"
+      "v_fma_f32 %[b0], %[a0], %[b0], %[d] mul:2\n\t"
+      "v_fma_f32 %[a1], %[a0], %[a1], %[h1] mul:2\n\t"
+      "v_fma_f32 %[a2], %[a0], %[a2], %[h2] mul:2\n\t"
+      "v_fma_f32 %[a3], %[a0], %[a3], %[h3] mul:2\n\t"
+      "v_fma_f32 %[a0], %[a0], %[a0], %[q]\n\t"
+      "v_fma_f32 %[q], -%[a1], %[a1], %[h0]\n\t"
+      "v_fma_f32 %[q], -%[a2], %[a2], %[q]\n\t"
+      "v_fma_f32 %[q], -%[a3], %[a3], %[q]\n\t"
+      "v_fma_f32 %[n], %[a0], %[a0], -%[q]\n\t"
+      "v_fmac_f32_e32 %[n], %[b0], %[b0]\n\t"
+      "v_fmac_f32_e32 %[n], %[b1], %[b1]\n\t"
+      "v_fmac_f32_e32 %[n], %[b2], %[b2]\n\t"
+      "v_fmac_f32_e32 %[n], %[b3], %[b3]"
+      : [a0] "+v"(z.a0), [a1] "+v"(z.a1), [a2] "+v"(z.a2), [a3] "+v"(z.a3), [b0] "+v"(z.b0),
+        [b1] "+v"(z.b1), [b2] "+v"(z.b2), [b3] "+v"(z.b3), [q] "+v"(q), [d] "=&v"(d),
+        [n] "=&v"(n)
+      : [h0] "v"(h[0]), [h1] "v"(h[1]), [h2] "v"(h[2]), [h3] "v"(h[3]), [h4] "v"(h[4]),
+        [h5] "v"(h[5]), [h6] "v"(h[6]), [h7] "v"(h[7]));
+  return n;
+}
+
+// The same arithmetic in C++ (the x2 written out: exact, so the values are those of
+// the asm form) for the real-part norm.
+template <int NORM>
+__device__ __forceinline__ float dq_update_q(DQ<float> &z, float &q, const float *h) {
+  if constexpr (NORM == 0) {
+    return dq_update_q_asm(z, q, h);
+  } else {
+    const float d = fmaf(-z.a1, z.b1, fmaf(-z.a2, z.b2, fmaf(-z.a3, z.b3, h[4])));
+    DQ<float> r;
+    r.b1 = 2.0f * fmaf(z.b0, z.a1, fmaf(z.a0, z.b1, h[5]));
+    r.b2 = 2.0f * fmaf(z.b0, z.a2, fmaf(z.a0, z.b2, h[6]));
+    r.b3 = 2.0f * fmaf(z.b0, z.a3, fmaf(z.a0, z.b3, h[7]));
+    r.b0 = 2.0f * fmaf(z.a0, z.b0, d);
+    r.a1 = 2.0f * fmaf(z.a0, z.a1, h[1]);
+    r.a2 = 2.0f * fmaf(z.a0, z.a2, h[2]);
+    r.a3 = 2.0f * fmaf(z.a0, z.a3, h[3]);
+    r.a0 = fmaf(z.a0, z.a0, q);
+    q = fmaf(-r.a3, r.a3, fmaf(-r.a2, r.a2, fmaf(-r.a1, r.a1, h[0])));
+    z = r;
+    return fmaf(r.a0, r.a0, -q);
+  }
+}
+
+// zeta_1 of a march sample on the identity slice, in closed form: zeta_0 =
+// (x, y, w, 0 | 0) gives zeta_1 = (x^2 - y^2 - w^2 + c0, 2xy + c1, 2xw + c2, c3 | c_d),
+// with q = (c0 - c3^2) - a1^2 - a2^2. The x2 is the output modifier again, and
+// c3..c7 are the halves doubled (exact), so no register holds the full constants.
+__device__ __forceinline__ void start_axis_q(float x, float y, float w, const float *h,
+                                             float c0c3, float &a0, DQ<float> &z, float &q) {
+  asm("v_fma_f32 %[a0], %[x], %[x], %[h0]\n\t"
+      "v_fma_f32 %[a1], %[x], %[y], %[h1] mul:2\n\t"
+      "v_fma_f32 %[a2], %[x], %[w], %[h2] mul:2\n\t"
+      "v_fma_f32 %[a0], -%[y], %[y], %[a0]\n\t"
+      "v_fma_f32 %[q], -%[a1], %[a1], %[c0c3]\n\t"
+      "v_fma_f32 %[a0], -%[w], %[w], %[a0]\n\t"
+      "v_fma_f32 %[q], -%[a2], %[a2], %[q]\n\t"
+      "v_add_f32_e32 %[a3], %[h3], %[h3]\n\t"
+      "v_add_f32_e32 %[b0], %[h4], %[h4]\n\t"
+      "v_add_f32_e32 %[b1], %[h5], %[h5]\n\t"
+      "v_add_f32_e32 %[b2], %[h6], %[h6]\n\t"
+      "v_add_f32_e32 %[b3], %[h7], %[h7]"
+      : [a0] "=&v"(a0), [a1] "=&v"(z.a1), [a2] "=&v"(z.a2), [a3] "=v"(z.a3), [b0] "=v"(z.b0),
+        [b1] "=v"(z.b1), [b2] "=v"(z.b2), [b3] "=v"(z.b3), [q] "=&v"(q)
+      : [x] "v"(x), [y] "v"(y), [w] "v"(w), [h0] "v"(h[0]), [h1] "v"(h[1]), [h2] "v"(h[2]),
+        [c0c3] "v"(c0c3), [h3] "v"(h[3]), [h4] "v"(h[4]), [h5] "v"(h[5]), [h6] "v"(h[6]),
+        [h7] "v"(h[7]));
+}
+
+// q = c0 - |a_v|^2 of a state.
+__device__ __forceinline__ float q_of(const DQ<float> &z, float c0) {
+  return fmaf(-z.a3, z.a3, fmaf(-z.a2, z.a2, fmaf(-z.a1, z.a1, c0)));
+}
+
+// zeta_0 for a world point and its q.
 template <bool AXIS>
 __device__ __forceinline__ void start_point(const KParams &P, float x, float y, float zc,
-                                            DQ<float> &z, float &s) {
-  if (AXIS) {
+                                            float c0, DQ<float> &z, float &q) {
+  if (AXIS)
     z = DQ<float>{x, y, zc, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    s = fmaf(zc, zc, y * y);
-  } else {
+  else
     z = slice_map<float>(P, x, y, zc);
-    s = vec_s(z);
-  }
+  q = q_of(z, c0);
 }
 
 }  // namespace
@@ -83,17 +187,15 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
   int next_r = 0;               // next ray of the tile to hand out
   bool have_tile = false, pending = false, exhausted = false;
   uint32_t pend_tile = 0;
-  float c[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) c[q] = 0.0f;
-  float R2 = 0.0f, c3sq = 0.0f, cdsq = 0.0f, Sfh = 0.0f;
+  float R2c = 0.0f, c0c3 = 0.0f, cdsq = 0.0f, Sfh = 0.0f;
   float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // eye (cached: the table is not provably read-only)
-  // Per-lane copies of c: the update and the closed-form start compute with vector
-  // registers only (scalar-register operands cost more issue time on gfx950). The eye,
-  // S - 1/2 and c3^2 below are per-lane copies for the same reason.
-  float cv[8];
+  // Per-lane copies of c0 and of c_i / 2 (i >= 1): the update and the closed-form
+  // start compute with vector registers only (scalar-register operands cost more issue
+  // time on gfx950). R^2 - c0, the eye, S - 1/2 and c0 - c3^2 below are per-lane
+  // copies for the same reason.
+  float h[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) cv[q] = 0.0f;
+  for (int i = 0; i < 8; ++i) h[i] = 0.0f;
   int N = 1;
   bool n_is_1 = false;
   // Trip counter: one update per trip. A point started in trip t has had trip - t
@@ -109,7 +211,7 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
   // deadline, so they never retire and need no separate test.
   int phase = PH_IDLE;
   DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
-  float s = kNaN;
+  float q = kNaN;
   uint32_t dl = kIdleAhead;
   int pix = 0;
   float dx = 0, dy = 0, dz = 0, t0 = 0, dt = 0;
@@ -118,31 +220,30 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
   float lo = 0, hi = 0, thit = 0, gx = 0, gy = 0, gz = 0;
   uint32_t it_lane = 0;
 
+  enter_update_mode();
   for (;;) {
     ++trip;
-    // ---- one update on every lane
-    float n2;
-    if constexpr (NORM == 0)
-      n2 = dq_update_inplace_v(z, s, cv);
-    else
-      n2 = dq_update<NORM>(z, s, cv);
-    const bool esc = n2 > R2;
-    // Fast path: an outside march sample with more samples to go starts the next one.
-    // Everything else that retires (a march hit or miss, a bisection or normal point)
-    // takes the slow path, which runs first: it never leaves a lane that would pass
-    // the fast test (it sets k past the march or idles the lane), so the fast test
-    // after it picks exactly the lanes it would have picked before.
-    // Each test is one select and one compare (k is integer-valued, so k >= S is
-    // k - (S - 0.5) >= 0): no scalar mask arithmetic on the hot path.
-    const float kq = k - Sfh;
-    const float xs = esc ? kq : (float)(int)(trip - dl);
+    // ---- one update on every lane (n2 is ||zeta||^2 - c0)
+    const float n2 = dq_update_q<NORM>(z, q, h);
+    // Three per-lane tests, combined as lane masks: the sample escaped, it is past the
+    // last march sample (k >= S; k is integer-valued, so k > S - 1/2), its deadline
+    // has come. Fast path: an outside march sample with more samples to go starts the
+    // next one. Everything else that retires (a march hit or miss, a bisection or
+    // normal point) takes the slow path, which runs first; the fast set is fixed
+    // before it, and the two sets are disjoint.
+    // (The masks are formed explicitly: left to itself the compiler turns the
+    // combination into per-lane selects.)
+    const uint64_t esc = __builtin_amdgcn_ballot_w64(n2 > R2c);
+    const uint64_t last = __builtin_amdgcn_ballot_w64(k > Sfh);
+    const uint64_t due = __builtin_amdgcn_ballot_w64((int)(trip - dl) >= 0);
+    const uint64_t fast = esc & ~last;
 
-    if (xs >= 0.0f) {
+    if (__builtin_amdgcn_inverse_ballot_w64((esc & last) | (due & ~esc))) {
       const KParams &P = F->P;
       // (recomputed from an opaque copy: a shared compare would run on every trip)
       float n2c = n2;
       asm volatile("" : "+v"(n2c));
-      const bool inside = !(n2c > R2);
+      const bool inside = !(n2c > R2c);
       const int m = N - (int)(dl - trip);   // escape index, or N when inside
       if (COUNT) it_lane += (uint32_t)m;
       bool next_normal = false;
@@ -187,7 +288,7 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
           restart = true;
         }
       } else {  // PH_NORMAL: stencil point sidx just retired
-        const float G = potential(n2, m);
+        const float G = potential(n2c + h[0], m);
         const float sg = (sidx & 1) ? -G : G;
         const int axis = sidx >> 1;
         if (axis == 0)
@@ -225,17 +326,16 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
         pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
       }
       if (phase != PH_IDLE) {
-        start_point<AXIS>(P, px, py, pz, z, s);
+        start_point<AXIS>(P, px, py, pz, h[0], z, q);
         dl = trip + (uint32_t)N;
       } else {
         z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
-        s = kNaN;
+        q = kNaN;
         dl = trip + kIdleAhead;
       }
     }
 
-    const float xf = esc ? kq : 1.0f;
-    if (xf < 0.0f) {
+    if (__builtin_amdgcn_inverse_ballot_w64(fast)) {
       if (COUNT) it_lane += (uint32_t)N - (dl - trip);
       k += 1.0f;
       const float t = fmaf(k, dt, t0);
@@ -243,18 +343,9 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
       const float y = fmaf(t, dy, ey);
       const float w = fmaf(t, dz, ez);
       if constexpr (AXIS) {
-        // First update in closed form: zeta_0 = (x, y, w, 0 | 0) gives
-        // zeta_1 = (x^2 - y^2 - w^2 + c0, 2xy + c1, 2xw + c2, c3 | c_d).
-        const float tx = x + x;
-        float a0 = fmaf(-w, w, fmaf(-y, y, fmaf(x, x, cv[0])));
-        z.a1 = fmaf(tx, y, cv[1]);
-        z.a2 = fmaf(tx, w, cv[2]);
-        z.a3 = cv[3];
-        z.b0 = cv[4];
-        z.b1 = cv[5];
-        z.b2 = cv[6];
-        z.b3 = cv[7];
-        s = fmaf(z.a2, z.a2, fmaf(z.a1, z.a1, c3sq));
+        // First update in closed form.
+        float a0;
+        start_axis_q(x, y, w, h, c0c3, a0, z, q);
         if constexpr (STICKY) {
           // zeta_2 escapes whenever zeta_1 does: leave zeta_1 untested (a sample that
           // escaped on it retires after the next update, as a parked one would).
@@ -263,13 +354,13 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
           // Test zeta_1. An escaped sample is parked on a state that escapes on the
           // next update (escape index 1); with max_iter 1 an inside one is parked on
           // NaN (never escapes) and retires on its deadline at the next trip.
-          const bool esc1 = fmaf(a0, a0, s + cdsq) > R2;
+          const bool esc1 = fmaf(a0, a0, cdsq - q) > R2c;
           a0 = esc1 ? 1e18f : (n_is_1 ? kNaN : a0);
           dl = trip + (uint32_t)(N - 1) + ((esc1 || n_is_1) ? 1u : 0u);
         }
         z.a0 = a0;
       } else {
-        start_point<AXIS>(F->P, x, y, w, z, s);
+        start_point<AXIS>(F->P, x, y, w, h[0], z, q);
         dl = trip + (uint32_t)N;
       }
     }
@@ -298,19 +389,20 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
           it_lane = 0;
           frame = f;
           if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
+          float c[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            c[q] = uniform_f(F->P.c[q]);
-            cv[q] = to_vgpr(c[q]);
-          }
-          R2 = uniform_f(F->P.R2);
+          for (int i = 0; i < 8; ++i) c[i] = uniform_f(F->P.c[i]);
+          h[0] = to_vgpr(c[0]);
+#pragma unroll
+          for (int i = 1; i < 8; ++i) h[i] = to_vgpr(uniform_f(0.5f * c[i]));
+          R2c = to_vgpr(uniform_f(F->P.R2 - c[0]));
           N = (int)uniform((uint32_t)F->P.N);
           n_is_1 = N == 1;
           ex = to_vgpr(uniform_f(F->P.eye[0]));
           ey = to_vgpr(uniform_f(F->P.eye[1]));
           ez = to_vgpr(uniform_f(F->P.eye[2]));
           Sfh = to_vgpr(uniform_f((float)F->P.S - 0.5f));
-          c3sq = to_vgpr(uniform_f(c[3] * c[3]));
+          c0c3 = to_vgpr(uniform_f(fmaf(-c[3], c[3], c[0])));
           cdsq = NORM == 0 ? uniform_f(fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))))
                            : 0.0f;
         }
@@ -343,7 +435,7 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
             kstar = -1;
             phase = PH_MARCH;
             z = DQ<float>{1e18f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            s = 0.0f;
+            q = 0.0f;
             dl = trip + (uint32_t)N;
             if (COUNT) it_lane -= 1u;
           } else {
