@@ -20,6 +20,7 @@
 #include "dq_device.h"
 #include "kparams.h"
 #include "persist.h"
+#include "qform.h"
 #include "runtime_internal.h"
 
 namespace dqj {
@@ -54,38 +55,34 @@ struct GridDesc {
 };
 
 // The square printed with Eq. dqjulia2: a' = a^2 + c_r, b' = b^2 + c_d, each quaternion
-// squared as (s, v)^2 = (s^2 - |v|^2, 2 s v) (Eq. quatsq). s carries |a_v|^2 as in the
-// dual update.
+// squared as (s, v)^2 = (s^2 - |v|^2, 2 s v) (Eq. quatsq), in the q form of the dual
+// update (q = c0 - |a_v|^2 carried, h the constant with h_i = c_i / 2 for i >= 1;
+// returns the norm minus c0).
 template <int NORM>
-__device__ __forceinline__ float dq_update_cw(DQ<float> &z, float &s, const float *c) {
-  const float ta = z.a0 + z.a0;
-  const float tb = z.b0 + z.b0;
-  const float sb = fmaf(z.b3, z.b3, fmaf(z.b2, z.b2, z.b1 * z.b1));
+__device__ __forceinline__ float dq_update_cw(DQ<float> &z, float &q, const float *h) {
+  const float qb = fmaf(-z.b3, z.b3, fmaf(-z.b2, z.b2, fmaf(-z.b1, z.b1, 2.0f * h[4])));
   DQ<float> r;
-  r.a0 = fmaf(z.a0, z.a0, c[0] - s);
-  r.a1 = fmaf(ta, z.a1, c[1]);
-  r.a2 = fmaf(ta, z.a2, c[2]);
-  r.a3 = fmaf(ta, z.a3, c[3]);
-  r.b0 = fmaf(z.b0, z.b0, c[4] - sb);
-  r.b1 = fmaf(tb, z.b1, c[5]);
-  r.b2 = fmaf(tb, z.b2, c[6]);
-  r.b3 = fmaf(tb, z.b3, c[7]);
-  const float s2 = fmaf(r.a3, r.a3, fmaf(r.a2, r.a2, r.a1 * r.a1));
-  float n2 = fmaf(r.a0, r.a0, s2);
+  r.a0 = fmaf(z.a0, z.a0, q);
+  r.a1 = 2.0f * fmaf(z.a0, z.a1, h[1]);
+  r.a2 = 2.0f * fmaf(z.a0, z.a2, h[2]);
+  r.a3 = 2.0f * fmaf(z.a0, z.a3, h[3]);
+  r.b0 = fmaf(z.b0, z.b0, qb);
+  r.b1 = 2.0f * fmaf(z.b0, z.b1, h[5]);
+  r.b2 = 2.0f * fmaf(z.b0, z.b2, h[6]);
+  r.b3 = 2.0f * fmaf(z.b0, z.b3, h[7]);
+  q = q_of(r, h[0]);
+  float n2 = fmaf(r.a0, r.a0, -q);
   if (NORM == 0) n2 = fmaf(r.b3, r.b3, fmaf(r.b2, r.b2, fmaf(r.b1, r.b1, fmaf(r.b0, r.b0, n2))));
   z = r;
-  s = s2;
   return n2;
 }
 
 template <int NORM, bool CW>
-__device__ __forceinline__ float grid_update(DQ<float> &z, float &s, const float *cv) {
+__device__ __forceinline__ float grid_update(DQ<float> &z, float &q, const float *h) {
   if constexpr (CW)
-    return dq_update_cw<NORM>(z, s, cv);
-  else if constexpr (NORM == 0)
-    return dq_update_inplace_v(z, s, cv);
+    return dq_update_cw<NORM>(z, q, h);
   else
-    return dq_update<NORM>(z, s, cv);
+    return dq_update_q<NORM>(z, q, h);
 }
 
 // zeta_0 of voxel x on the run (y, z): on the identity slice zeta_1 in closed form,
@@ -97,31 +94,23 @@ __device__ __forceinline__ float grid_update(DQ<float> &z, float &s, const float
 // not kept.
 template <bool AXIS, bool STICKY>
 __device__ __forceinline__ void start_voxel(const KParams &P, float x, float yw, float zw,
-                                            const float *cv, float c3sq, float cdsq, float R2,
+                                            const float *h, float c0c3, float cdsq, float R2c,
                                             int N, bool n_is_1, uint32_t trip, DQ<float> &z,
-                                            float &s, uint32_t &dl) {
+                                            float &q, uint32_t &dl) {
   if constexpr (AXIS) {
-    const float tx = x + x;
-    float a0 = fmaf(-zw, zw, fmaf(-yw, yw, fmaf(x, x, cv[0])));
-    z.a1 = fmaf(tx, yw, cv[1]);
-    z.a2 = fmaf(tx, zw, cv[2]);
-    z.a3 = cv[3];
-    z.b0 = cv[4];
-    z.b1 = cv[5];
-    z.b2 = cv[6];
-    z.b3 = cv[7];
-    s = fmaf(z.a2, z.a2, fmaf(z.a1, z.a1, c3sq));
+    float a0;
+    start_axis_q(x, yw, zw, h, c0c3, a0, z, q);
     if constexpr (STICKY) {
       dl = trip + (uint32_t)(N - 1);
     } else {
-      const bool esc1 = fmaf(a0, a0, s + cdsq) > R2;
+      const bool esc1 = fmaf(a0, a0, cdsq - q) > R2c;
       a0 = esc1 ? 1e18f : (n_is_1 ? __builtin_nanf("") : a0);
       dl = trip + (uint32_t)(N - 1) + ((esc1 || n_is_1) ? 1u : 0u);
     }
     z.a0 = a0;
   } else {
     z = slice_map<float>(P, x, yw, zw);
-    s = vec_s(z);
+    q = q_of(z, h[0]);
     dl = trip + (uint32_t)N;
   }
 }
@@ -134,17 +123,19 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
   const int lane = lane_id();
   const float kNaN = __builtin_nanf("");
   const uint32_t kIdleAhead = 0x7FFFFFFFu;
-  float cv[8];
+  // per-lane copies of c0 and c_i / 2 (the q form), of R^2 - c0 and of c0 - c3^2
+  float h[8];
+  h[0] = to_vgpr(G.P.c[0]);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(G.P.c[q]);
-  const float R2 = G.P.R2;
+  for (int q = 1; q < 8; ++q) h[q] = to_vgpr(0.5f * G.P.c[q]);
+  const float R2c = to_vgpr(G.P.R2 - G.P.c[0]);
   const int N = G.P.N;
   const bool n_is_1 = N == 1;
   // |c_d|^2: the dual part of zeta_1 on the identity slice is c_d under both algebras
   const float cdsq = NORM == 0 ? fmaf(G.P.c[7], G.P.c[7], fmaf(G.P.c[6], G.P.c[6],
                                       fmaf(G.P.c[5], G.P.c[5], G.P.c[4] * G.P.c[4])))
                                : 0.0f;
-  const float c3sq = G.P.c[3] * G.P.c[3];
+  const float c0c3 = to_vgpr(fmaf(-G.P.c[3], G.P.c[3], G.P.c[0]));
   const float x0 = to_vgpr(G.x0), dx = to_vgpr(G.dx);
 
   // wave-uniform hand-out state
@@ -154,7 +145,7 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
   // per-lane state: an idle lane sits on NaN (never escapes) with a far deadline
   uint32_t trip = 0;
   DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
-  float s = kNaN;
+  float q = kNaN;
   uint32_t dl = kIdleAhead;
   uint64_t v = 0, vend = 0;        // current voxel (memory order) and end of the run's segment
   int i = 0, j = 0, k = 0;         // grid coordinates of v
@@ -162,10 +153,11 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
   const int stride = G.stride, nx = G.nx, ny = G.ny;
   unsigned long long it_lane = 0;
 
+  enter_update_mode();
   for (;;) {
     ++trip;
-    const float n2 = grid_update<NORM, CW>(z, s, cv);
-    const bool esc = n2 > R2;
+    const float n2 = grid_update<NORM, CW>(z, q, h);   // norm minus c0
+    const bool esc = n2 > R2c;
     if (esc || (int)(trip - dl) >= 0) {
       // the voxel retires: escape index m, or N when it stayed inside
       G.mask[v] = esc ? 0 : 1;
@@ -188,8 +180,8 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
       k += wrapj ? 1 : 0;
       yw = fmaf((float)j, G.dy, G.y0);
       zw = fmaf((float)k, G.dz, G.z0);
-      start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, cv, c3sq, cdsq, R2, N,
-                                n_is_1, trip, z, s, dl);
+      start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, h, c0c3, cdsq, R2c, N,
+                                n_is_1, trip, z, q, dl);
     }
 
     // ---- hand runs to idle lanes (rare: a run lasts dozens of trips)
@@ -212,10 +204,10 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
         const uint32_t avail = kChunk - next_r;
         const uint32_t rank = (uint32_t)rank_in(idle);
         if (v >= vend && rank < avail) {
-          const uint32_t q = next_r + rank;               // run within the chunk
-          const uint64_t seg = (uint64_t)chunk * (kChunk / stride) + q / stride;
+          const uint32_t run = next_r + rank;             // run within the chunk
+          const uint64_t seg = (uint64_t)chunk * (kChunk / stride) + run / stride;
           const uint64_t s0 = seg * (uint64_t)stride * kPer;
-          v = s0 + q % stride;
+          v = s0 + run % stride;
           vend = min(s0 + (uint64_t)stride * kPer, G.nvox);   // v >= vend: an empty run
           const uint64_t row = v / (uint64_t)nx;
           i = (int)(v - row * (uint64_t)nx);
@@ -223,8 +215,8 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
           k = (int)(row / (uint64_t)ny);
           yw = fmaf((float)j, G.dy, G.y0);
           zw = fmaf((float)k, G.dz, G.z0);
-          start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, cv, c3sq, cdsq, R2, N,
-                                    n_is_1, trip, z, s, dl);
+          start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, h, c0c3, cdsq, R2c, N,
+                                    n_is_1, trip, z, q, dl);
         }
         const uint32_t cnt = (uint32_t)__popcll(idle);
         next_r += cnt < avail ? cnt : avail;
@@ -234,7 +226,7 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
       // lanes left without a run sit on NaN (never escapes) with a far deadline
       if (v >= vend) {
         z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
-        s = kNaN;
+        q = kNaN;
         dl = trip + kIdleAhead;
       }
       if (exhausted && !__builtin_amdgcn_ballot_w64(v < vend)) break;
