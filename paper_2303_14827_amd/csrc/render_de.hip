@@ -22,6 +22,7 @@
 #include "dq_device.h"
 #include "launch.h"
 #include "persist.h"
+#include "qform.h"
 #include "refill.h"
 #include <cstring>
 
@@ -29,33 +30,48 @@ namespace dqj {
 
 namespace {
 
-// zeta_0 of a world point and |a_v|^2 of it (identity slice: (x, y, w, 0 | 0)).
-template <bool AXIS>
-__device__ __forceinline__ void de_start(const KParams &P, float x, float y, float w, DQ<float> &z,
-                                         float &s) {
-  if (AXIS) {
-    z = DQ<float>{x, y, w, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    s = fmaf(w, w, y * y);
-  } else {
-    z = slice_map<float>(P, x, y, w);
-    s = vec_s(z);
-  }
+// The march points iterate the q-form update (q = c0 - |a_v|^2 carried; norms are
+// held minus c0 and tested against R^2 - c0). Per-lane copies of its constants: h
+// (c0 and c_i / 2), R^2 - c0, 1 / R^2 and c0 / R^2 (for the derivative factor
+// |z_n|^2 / R^2 = (n - c0) / R^2 + c0 / R^2 of a held norm n).
+struct QConst {
+  float h[8];
+  float R2c, inv_r2, c0r;
+};
+
+__device__ __forceinline__ void load_qconst(const KParams &P, QConst &K) {
+  using persist::uniform_f;
+  K.h[0] = to_vgpr(uniform_f(P.c[0]));
+#pragma unroll
+  for (int i = 1; i < 8; ++i) K.h[i] = to_vgpr(uniform_f(0.5f * P.c[i]));
+  K.R2c = to_vgpr(uniform_f(P.R2 - P.c[0]));
+  K.inv_r2 = to_vgpr(uniform_f(P.de_inv_r2));
+  K.c0r = to_vgpr(uniform_f(P.c[0] * P.de_inv_r2));
 }
 
+// zeta_0 of a world point and its q (identity slice: (x, y, w, 0 | 0)).
+template <bool AXIS>
+__device__ __forceinline__ void de_start(const KParams &P, float x, float y, float w, float c0,
+                                         DQ<float> &z, float &q) {
+  if (AXIS)
+    z = DQ<float>{x, y, w, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  else
+    z = slice_map<float>(P, x, y, w);
+  q = q_of(z, c0);
+}
+
+// ||z||^2 - c0 of a state under NORM.
 template <int NORM>
-__device__ __forceinline__ float norm2_of(const DQ<float> &z, float s) {
-  float n2 = fmaf(z.a0, z.a0, s);
+__device__ __forceinline__ float norm2_of(const DQ<float> &z, float q) {
+  float n2 = fmaf(z.a0, z.a0, -q);
   if (NORM == 0) n2 = fmaf(z.b3, z.b3, fmaf(z.b2, z.b2, fmaf(z.b1, z.b1, fmaf(z.b0, z.b0, n2))));
   return n2;
 }
 
-// One update with c in vector registers (in place for the 8-square norm).
+// One update (returns the new norm minus c0).
 template <int NORM>
-__device__ __forceinline__ float de_update(DQ<float> &z, float &s, const float *cv) {
-  if constexpr (NORM == 0)
-    return dq_update_inplace_v(z, s, cv);
-  else
-    return dq_update<NORM>(z, s, cv);
+__device__ __forceinline__ float de_update(DQ<float> &z, float &q, const float *h) {
+  return dq_update_q<NORM>(z, q, h);
 }
 
 // Estimate 0.5 |z_m| ln|z_m| / |z'_m| from n2 = |z_m|^2 and D = D_m:
@@ -70,21 +86,22 @@ __device__ __forceinline__ float de_estimate(float n2, float D, int m, float log
 // *n2out (|z_N|^2 when inside) and, when DE, the distance estimate of an escaping point
 // in *de. The estimate is formed once, after the loop.
 template <int NORM, bool DE>
-__device__ __forceinline__ int classify_de(const KParams &P, const float *cv, DQ<float> z, float s,
+__device__ __forceinline__ int classify_de(const KParams &P, const QConst &K, DQ<float> z, float q,
                                            float *de, float *n2out) {
-  float n2 = norm2_of<NORM>(z, s);
+  float n2 = norm2_of<NORM>(z, q);
   float D = 1.0f;
   int n = 0;
   bool esc = false;
   while (n < P.N) {
     ++n;
-    if (DE) D = D * (n2 * P.de_inv_r2);
-    n2 = de_update<NORM>(z, s, cv);
-    if (n2 > P.R2) {
+    if (DE) D = D * fmaf(n2, K.inv_r2, K.c0r);
+    n2 = de_update<NORM>(z, q, K.h);
+    if (n2 > K.R2c) {
       esc = true;
       break;
     }
   }
+  n2 += K.h[0];
   *n2out = n2;
   if (!esc) return 0;
   if (DE) *de = de_estimate(n2, D, n, P.de_log2_4r2);
@@ -92,7 +109,7 @@ __device__ __forceinline__ int classify_de(const KParams &P, const float *cv, DQ
 }
 
 template <int NORM, bool AXIS>
-__device__ void render_pixel_de(const KParams &P, const float *cv, int i, int j, PixelOut &r,
+__device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j, PixelOut &r,
                                 unsigned long long &iters) {
   float d[3];
   pixel_dir(P, i, j, d);
@@ -107,10 +124,11 @@ __device__ void render_pixel_de(const KParams &P, const float *cv, int i, int j,
   float t = t0, tprev = t0;
   for (int k = 0; k < P.S; ++k) {
     DQ<float> z;
-    float s;
-    de_start<AXIS>(P, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]), fmaf(t, d[2], P.eye[2]), z, s);
+    float q;
+    de_start<AXIS>(P, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]), fmaf(t, d[2], P.eye[2]),
+                   K.h[0], z, q);
     float de = 0.0f, n2;
-    const int m = classify_de<NORM, true>(P, cv, z, s, &de, &n2);
+    const int m = classify_de<NORM, true>(P, K, z, q, &de, &n2);
     iters += m ? m : P.N;
     if (m == 0) {   // inside: the hit is t0 on the first point, else bisect the last step
       kstar = k;
@@ -139,10 +157,10 @@ __device__ void render_pixel_de(const KParams &P, const float *cv, int i, int j,
     for (int b = 0; b < P.B; ++b) {
       const float tm = 0.5f * (lo + hi);
       DQ<float> z;
-      float s, n2, unused;
+      float q, n2, unused;
       de_start<AXIS>(P, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]), fmaf(tm, d[2], P.eye[2]),
-                     z, s);
-      const int m = classify_de<NORM, false>(P, cv, z, s, &unused, &n2);
+                     K.h[0], z, q);
+      const int m = classify_de<NORM, false>(P, K, z, q, &unused, &n2);
       iters += m ? m : P.N;
       if (m == 0)
         hi = tm;
@@ -164,9 +182,9 @@ __device__ void render_pixel_de(const KParams &P, const float *cv, int i, int j,
       float x[3] = {ph[0], ph[1], ph[2]};
       x[a] = sgn == 0 ? ph[a] + P.h : ph[a] - P.h;
       DQ<float> z;
-      float s, n2, unused;
-      de_start<AXIS>(P, x[0], x[1], x[2], z, s);
-      int m = classify_de<NORM, false>(P, cv, z, s, &unused, &n2);
+      float q, n2, unused;
+      de_start<AXIS>(P, x[0], x[1], x[2], K.h[0], z, q);
+      int m = classify_de<NORM, false>(P, K, z, q, &unused, &n2);
       m = m ? m : P.N;
       iters += m;
       const float G = potential(n2, m);
@@ -184,13 +202,13 @@ template <int NORM, bool AXIS>
 __device__ __forceinline__ void render_de_block(const KParams &P, const KOut &out) {
   const int i = blockIdx.x * 16 + (threadIdx.x & 15);
   const int j = blockIdx.y * (blockDim.x >> 4) + (threadIdx.x >> 4);
-  float cv[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(P.c[q]);
+  enter_update_mode();
+  QConst K;
+  load_qconst(P, K);
   unsigned long long iters = 0;
   if (i < P.W && j < P.H) {
     PixelOut r;
-    render_pixel_de<NORM, AXIS>(P, cv, i, j, r, iters);
+    render_pixel_de<NORM, AXIS>(P, K, i, j, r, iters);
     write_pixel(out, (int64_t)j * P.W + i, r);
   }
   if (out.iters) wave_add_u64(out.iters, iters);
@@ -298,11 +316,12 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
   int next_r = 0;
   bool have_tile = false, pending = false, exhausted = false;
   uint32_t pend_tile = 0;
-  float cv[8];   // per-lane copies of c (vector-register operands issue faster)
+  QConst K;     // per-lane copies of the update's constants (vector-register operands)
 #pragma unroll
-  for (int q = 0; q < 8; ++q) cv[q] = 0.0f;
-  float R2 = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
-  float inv_r2 = 0.0f, l4r2 = 0.0f, eps = 0.0f, smin = 0.0f, smax = 0.0f;
+  for (int i = 0; i < 8; ++i) K.h[i] = 0.0f;
+  K.R2c = K.inv_r2 = K.c0r = 0.0f;
+  float ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  float l4r2 = 0.0f, eps = 0.0f, smin = 0.0f, smax = 0.0f;
   int N = 1, S = 1;
   // trip counter and deadlines as in render_refill_kernel
   uint32_t trip = 0;
@@ -310,9 +329,9 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
 
   int phase = DE_IDLE;
   DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
-  float s = kNaN;
+  float q = kNaN;
   float D = 1.0f;          // |z'_n|^2 / (4 R^2)^n of the current march point
-  float n2prev = 0.0f;     // |z_n|^2 of the current point (the next derivative step needs it)
+  float n2prev = 0.0f;     // |z_n|^2 - c0 of the current point (the next derivative step needs it)
   uint32_t dl = kIdleAhead;
   int pix = 0;
   float dx = 0, dy = 0, dz = 0, t0 = 0, t1 = 0, t = 0, tprev = 0;
@@ -320,13 +339,14 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
   float lo = 0, hi = 0, thit = 0, gx = 0, gy = 0, gz = 0;
   uint32_t it_lane = 0;
 
+  enter_update_mode();
   for (;;) {
     ++trip;
     // ---- one update on every lane, the derivative norm carried along
-    D = D * (n2prev * inv_r2);
-    const float n2 = de_update<NORM>(z, s, cv);
+    D = D * fmaf(n2prev, K.inv_r2, K.c0r);
+    const float n2 = de_update<NORM>(z, q, K.h);   // norm minus c0
     n2prev = n2;
-    const bool esc = n2 > R2;
+    const bool esc = n2 > K.R2c;
     const bool expired = (int)(trip - dl) >= 0;
 
     // ---- an escaped march point: its distance estimate and the next step
@@ -334,7 +354,7 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
     float de = 0.0f;
     if (esc && phase == DE_MARCH) {
       const int m = N - (int)(dl - trip);
-      de = de_estimate(n2, D, m, l4r2);
+      de = de_estimate(n2 + K.h[0], D, m, l4r2);
       const float tn = t + fminf(fmaxf(de, smin), smax);
       fast = de >= eps && tn <= t1 && k + 1 < S;
       if (fast) {
@@ -342,8 +362,8 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
         tprev = t;
         t = tn;
         ++k;
-        de_start<AXIS>(F->P, fmaf(t, dx, ex), fmaf(t, dy, ey), fmaf(t, dz, ez), z, s);
-        n2prev = norm2_of<NORM>(z, s);
+        de_start<AXIS>(F->P, fmaf(t, dx, ex), fmaf(t, dy, ey), fmaf(t, dz, ez), K.h[0], z, q);
+        n2prev = norm2_of<NORM>(z, q);
         D = 1.0f;
         dl = trip + (uint32_t)N;
       }
@@ -354,7 +374,7 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
       const KParams &P = F->P;
       float n2c = n2;
       asm volatile("" : "+v"(n2c));
-      const bool inside = !(n2c > R2);
+      const bool inside = !(n2c > K.R2c);
       const int m = N - (int)(dl - trip);
       if (COUNT) it_lane += (uint32_t)m;
       bool next_normal = false, restart = false;
@@ -401,7 +421,7 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
           restart = true;
         }
       } else {   // DE_NORMAL: stencil point sidx just retired
-        const float G = potential(n2, m);
+        const float G = potential(n2c + K.h[0], m);
         const float sg = (sidx & 1) ? -G : G;
         const int axis = sidx >> 1;
         if (axis == 0)
@@ -439,11 +459,11 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
         pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
       }
       if (phase != DE_IDLE) {
-        de_start<AXIS>(P, px, py, pz, z, s);
+        de_start<AXIS>(P, px, py, pz, K.h[0], z, q);
         dl = trip + (uint32_t)N;
       } else {
         z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
-        s = kNaN;
+        q = kNaN;
         dl = trip + kIdleAhead;
       }
     }
@@ -471,15 +491,12 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
           it_lane = 0;
           frame = f;
           if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(uniform_f(F->P.c[q]));
-          R2 = uniform_f(F->P.R2);
+          load_qconst(F->P, K);
           N = (int)uniform((uint32_t)F->P.N);
           S = (int)uniform((uint32_t)F->P.S);
           ex = uniform_f(F->P.eye[0]);
           ey = uniform_f(F->P.eye[1]);
           ez = uniform_f(F->P.eye[2]);
-          inv_r2 = uniform_f(F->P.de_inv_r2);
           l4r2 = uniform_f(F->P.de_log2_4r2);
           eps = uniform_f(F->P.de_eps);
           smin = uniform_f(F->P.de_min_step);
@@ -513,8 +530,8 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
             k = 0;
             kstar = -1;
             phase = DE_MARCH;
-            de_start<AXIS>(P, fmaf(t, dx, ex), fmaf(t, dy, ey), fmaf(t, dz, ez), z, s);
-            n2prev = norm2_of<NORM>(z, s);
+            de_start<AXIS>(P, fmaf(t, dx, ex), fmaf(t, dy, ey), fmaf(t, dz, ez), K.h[0], z, q);
+            n2prev = norm2_of<NORM>(z, q);
             D = 1.0f;
             dl = trip + (uint32_t)N;
           } else {
@@ -546,10 +563,10 @@ __global__ __launch_bounds__(1024) void render_de_lockstep_kernel(FrameDesc F, u
   const KParams &P = F.P;
   const int lane = lane_id();
   const int tile_rays = TW * TH;
-  float cv[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) cv[q] = to_vgpr(P.c[q]);
-  const float R2 = P.R2, inv_r2 = P.de_inv_r2, l4r2 = P.de_log2_4r2;
+  enter_update_mode();
+  QConst K;
+  load_qconst(P, K);
+  const float l4r2 = P.de_log2_4r2;
   const float eps = P.de_eps, smin = P.de_min_step, smax = P.de_max_step;
   const float ex = P.eye[0], ey = P.eye[1], ez = P.eye[2];
   const int N = P.N, S = P.S, B = P.B;
@@ -626,19 +643,20 @@ __global__ __launch_bounds__(1024) void render_de_lockstep_kernel(FrameDesc F, u
     bool inside = true;
     if (phase != DE_IDLE) {
       DQ<float> z;
-      float sv;
-      de_start<AXIS>(P, px, py, pz, z, sv);
-      n2 = norm2_of<NORM>(z, sv);
+      float qv;
+      de_start<AXIS>(P, px, py, pz, K.h[0], z, qv);
+      n2 = norm2_of<NORM>(z, qv);
       int n = 0;
       while (n < N) {
         ++n;
-        D = D * (n2 * inv_r2);
-        n2 = de_update<NORM>(z, sv, cv);
-        if (n2 > R2) {
+        D = D * fmaf(n2, K.inv_r2, K.c0r);
+        n2 = de_update<NORM>(z, qv, K.h);
+        if (n2 > K.R2c) {
           inside = false;
           break;
         }
       }
+      n2 += K.h[0];
       m = inside ? N : n;
       if (COUNT) it_lane += (unsigned long long)m;
     }
