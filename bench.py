@@ -41,20 +41,22 @@ FP32_FMAC_ISSUE_TFLOPS = 113.2
 TRAFFIC_RECORDS = {
     "plain": {
         "sources": ["paper_2303_14827_amd/csrc/render_refill.hip", "paper_2303_14827_amd/csrc/persist.h",
+                    "paper_2303_14827_amd/csrc/qform.h",
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "a35a22427324d3a85e82c8c7ac3221642c76ae8456c50e50981719642a2408b8",
-        "fetch_kib": 63.40, "fetch_factor": 2.0, "write_kib": 37506.27, "write_factor": 1.0,
+        "sources_sha256": "4f6eeba1521476c0d28011682f13bb1c9ec6902f963f7b0a2633adf0d7a0169b",
+        "fetch_kib": 69.21, "fetch_factor": 2.0, "write_kib": 37560.08, "write_factor": 1.0,
     },
     "voxel": {
         "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
+                    "paper_2303_14827_amd/csrc/qform.h",
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "baceaab2d3250d7cc32b2649502abf1a84726dd69382c0111639e3bd157866c5",
-        "fetch_kib": 1255.42, "fetch_factor": 2.0, "write_kib": 2764216.25, "write_factor": 1.0,
+        "sources_sha256": "0d5c92e30e00bad6920be5f30ce10a228ca4f310f553322c468e5eb53a8be46b",
+        "fetch_kib": 1426.02, "fetch_factor": 2.0, "write_kib": 3026410.22, "write_factor": 1.0,
     },
 }
 
