@@ -12,7 +12,7 @@ FP64 oracle (tests/golden/ialg_plain_1024.json), and t the wall time per step.
 Each update is priced at 52 FP32 flops (37 for z^2 + c, 15 for the 8-square norm)
 for the roofline against the FP32 vector peak.
 
-Prints ONE JSON line. ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line. ``--gpus N`` with N > 1 exits: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -46,7 +46,7 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "4f6eeba1521476c0d28011682f13bb1c9ec6902f963f7b0a2633adf0d7a0169b",
+        "sources_sha256": "7bf548b48d221c57eed08c694bbe0e62786dfd51f72c71134aa4794d7f4d63ce",
         "fetch_kib": 69.21, "fetch_factor": 2.0, "write_kib": 37560.08, "write_factor": 1.0,
     },
     "voxel": {
@@ -55,7 +55,7 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "0d5c92e30e00bad6920be5f30ce10a228ca4f310f553322c468e5eb53a8be46b",
+        "sources_sha256": "18b969c5b47639b554d6eb4a02d61059f019e829e3820e515e09914a8cb81ade",
         "fetch_kib": 1426.02, "fetch_factor": 2.0, "write_kib": 3026410.22, "write_factor": 1.0,
     },
 }
@@ -550,7 +550,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(every pixel, frame and request is independent: see the sharding design)",
               file=sys.stderr)
         sys.exit(2)

@@ -52,7 +52,7 @@ enum {
   DQJ_E_DEVICE = -5,       /* HIP runtime or kernel error */
   DQJ_E_TIMEOUT = -6,
   DQJ_E_CANCELLED = -7,
-  DQJ_E_UNSUPPORTED = -8,  /* no gfx950 device, or a mode this build does not offer */
+  DQJ_E_UNSUPPORTED = -8,  /* no gfx950 device, or a mode the library does not offer */
   DQJ_E_STATE = -9         /* call not valid in the object's current state */
 };
 

@@ -214,7 +214,7 @@ __device__ __forceinline__ bool clip_sphere(const P_T &P, const T d[3], T &tn, T
 
 // x^s for 0 < x <= 1 as exp2(s log2 x) on the hardware transcendental units: relative
 // error a few ulp times s |log2 x|, far inside a shade quantum (shades are stored in
-// FP32 and judged to 1/255). The FP64 path takes it in FP32 too: an FP64 pow would
+// FP32 and compared to 1/255). The FP64 path takes it in FP32 too: an FP64 pow would
 // raise that kernel's register count by a quarter for one term of the shade.
 __device__ __forceinline__ float spec_pow(float x, float s) {
   return __builtin_amdgcn_exp2f(s * __builtin_amdgcn_logf(x));
