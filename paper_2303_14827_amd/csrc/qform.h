@@ -108,6 +108,30 @@ __device__ __forceinline__ void start_axis_q(float x, float y, float w, const fl
         [h7] "v"(h[7]));
 }
 
+// The same start with c3..c7 copied from vector registers holding the full constants
+// (for kernels with registers to spare: a move issues faster than the doubling).
+__device__ __forceinline__ void start_axis_q_mov(float x, float y, float w, const float *h,
+                                                 const float *c, float c0c3, float &a0,
+                                                 DQ<float> &z, float &q) {
+  asm("v_fma_f32 %[a0], %[x], %[x], %[h0]\n\t"
+      "v_fma_f32 %[a1], %[x], %[y], %[h1] mul:2\n\t"
+      "v_fma_f32 %[a2], %[x], %[w], %[h2] mul:2\n\t"
+      "v_fma_f32 %[a0], -%[y], %[y], %[a0]\n\t"
+      "v_fma_f32 %[q], -%[a1], %[a1], %[c0c3]\n\t"
+      "v_fma_f32 %[a0], -%[w], %[w], %[a0]\n\t"
+      "v_fma_f32 %[q], -%[a2], %[a2], %[q]\n\t"
+      "v_mov_b32 %[a3], %[c3]\n\t"
+      "v_mov_b32 %[b0], %[c4]\n\t"
+      "v_mov_b32 %[b1], %[c5]\n\t"
+      "v_mov_b32 %[b2], %[c6]\n\t"
+      "v_mov_b32 %[b3], %[c7]"
+      : [a0] "=&v"(a0), [a1] "=&v"(z.a1), [a2] "=&v"(z.a2), [a3] "=v"(z.a3), [b0] "=v"(z.b0),
+        [b1] "=v"(z.b1), [b2] "=v"(z.b2), [b3] "=v"(z.b3), [q] "=&v"(q)
+      : [x] "v"(x), [y] "v"(y), [w] "v"(w), [h0] "v"(h[0]), [h1] "v"(h[1]), [h2] "v"(h[2]),
+        [c0c3] "v"(c0c3), [c3] "v"(c[3]), [c4] "v"(c[4]), [c5] "v"(c[5]), [c6] "v"(c[6]),
+        [c7] "v"(c[7]));
+}
+
 // q = c0 - |a_v|^2 of a state.
 __device__ __forceinline__ float q_of(const DQ<float> &z, float c0) {
   return fmaf(-z.a3, z.a3, fmaf(-z.a2, z.a2, fmaf(-z.a1, z.a1, c0)));

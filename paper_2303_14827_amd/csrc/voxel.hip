@@ -94,12 +94,13 @@ __device__ __forceinline__ float grid_update(DQ<float> &z, float &q, const float
 // not kept.
 template <bool AXIS, bool STICKY>
 __device__ __forceinline__ void start_voxel(const KParams &P, float x, float yw, float zw,
-                                            const float *h, float c0c3, float cdsq, float R2c,
+                                            const float *h, const float *cf, float c0c3,
+                                            float cdsq, float R2c,
                                             int N, bool n_is_1, uint32_t trip, DQ<float> &z,
                                             float &q, uint32_t &dl) {
   if constexpr (AXIS) {
     float a0;
-    start_axis_q(x, yw, zw, h, c0c3, a0, z, q);
+    start_axis_q_mov(x, yw, zw, h, cf, c0c3, a0, z, q);
     if constexpr (STICKY) {
       dl = trip + (uint32_t)(N - 1);
     } else {
@@ -129,6 +130,9 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
 #pragma unroll
   for (int q = 1; q < 8; ++q) h[q] = to_vgpr(0.5f * G.P.c[q]);
   const float R2c = to_vgpr(G.P.R2 - G.P.c[0]);
+  float cf[8];   // c3..c7 in full, for the closed-form start
+#pragma unroll
+  for (int q = 0; q < 8; ++q) cf[q] = q >= 3 ? to_vgpr(G.P.c[q]) : 0.0f;
   const int N = G.P.N;
   const bool n_is_1 = N == 1;
   // |c_d|^2: the dual part of zeta_1 on the identity slice is c_d under both algebras
@@ -136,7 +140,11 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
                                       fmaf(G.P.c[5], G.P.c[5], G.P.c[4] * G.P.c[4])))
                                : 0.0f;
   const float c0c3 = to_vgpr(fmaf(-G.P.c[3], G.P.c[3], G.P.c[0]));
+  // the grid's axes and sizes, also as per-lane copies (the retire step reads them on
+  // nearly every trip; scalar-register operands would cost a move or a slower issue)
   const float x0 = to_vgpr(G.x0), dx = to_vgpr(G.dx);
+  const float y0 = to_vgpr(G.y0), dy = to_vgpr(G.dy);
+  const float z0 = to_vgpr(G.z0), dz = to_vgpr(G.dz);
 
   // wave-uniform hand-out state
   uint32_t chunk = 0, next_r = 0;
@@ -147,10 +155,13 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
   DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
   float q = kNaN;
   uint32_t dl = kIdleAhead;
-  uint64_t v = 0, vend = 0;        // current voxel (memory order) and end of the run's segment
-  int i = 0, j = 0, k = 0;         // grid coordinates of v
+  // the current voxel's mask byte and the end of its run's segment (memory order)
+  uint8_t *pv = G.mask, *pend = G.mask;
+  int i = 0, j = 0, k = 0;         // grid coordinates of the current voxel
   float yw = 0.0f, zw = 0.0f;      // world y, z of row (j, k)
-  const int stride = G.stride, nx = G.nx, ny = G.ny;
+  const int stride = G.stride;
+  const int nx = (int)__float_as_uint(to_vgpr(__uint_as_float((uint32_t)G.nx)));
+  const int ny = (int)__float_as_uint(to_vgpr(__uint_as_float((uint32_t)G.ny)));
   unsigned long long it_lane = 0;
 
   enter_update_mode();
@@ -160,17 +171,17 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
     const bool esc = n2 > R2c;
     if (esc || (int)(trip - dl) >= 0) {
       // the voxel retires: escape index m, or N when it stayed inside
-      G.mask[v] = esc ? 0 : 1;
+      *pv = esc ? 0 : 1;
       if (EXTRA) {
         const int m = N - (int)(dl - trip);
-        if (G.escape) G.escape[v] = esc ? m : 0;
+        if (G.escape) G.escape[pv - G.mask] = esc ? m : 0;
         it_lane += (unsigned long long)m;
       }
       // Start the next voxel of the run. A lane that has just passed the end of its run
       // starts a voxel it never retires: the hand-out below, in this same trip, gives it
       // a new run or parks it.
       // step to the run's next voxel; at most one row end lies in between
-      v += (uint64_t)stride;
+      pv += stride;
       i += stride;
       const bool wrap = i >= nx;
       i = wrap ? i - nx : i;
@@ -178,14 +189,14 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
       const bool wrapj = j >= ny;
       j = wrapj ? 0 : j;
       k += wrapj ? 1 : 0;
-      yw = fmaf((float)j, G.dy, G.y0);
-      zw = fmaf((float)k, G.dz, G.z0);
-      start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, h, c0c3, cdsq, R2c, N,
+      yw = fmaf((float)j, dy, y0);
+      zw = fmaf((float)k, dz, z0);
+      start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, h, cf, c0c3, cdsq, R2c, N,
                                 n_is_1, trip, z, q, dl);
     }
 
     // ---- hand runs to idle lanes (rare: a run lasts dozens of trips)
-    uint64_t idle = __builtin_amdgcn_ballot_w64(v >= vend);
+    uint64_t idle = __builtin_amdgcn_ballot_w64(pv >= pend);
     if (idle) {
       while (idle) {
         if (!have_chunk) {
@@ -203,33 +214,34 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
         }
         const uint32_t avail = kChunk - next_r;
         const uint32_t rank = (uint32_t)rank_in(idle);
-        if (v >= vend && rank < avail) {
+        if (pv >= pend && rank < avail) {
           const uint32_t run = next_r + rank;             // run within the chunk
           const uint64_t seg = (uint64_t)chunk * (kChunk / stride) + run / stride;
           const uint64_t s0 = seg * (uint64_t)stride * kPer;
-          v = s0 + run % stride;
-          vend = min(s0 + (uint64_t)stride * kPer, G.nvox);   // v >= vend: an empty run
+          const uint64_t v = s0 + run % stride;
+          pv = G.mask + v;
+          pend = G.mask + min(s0 + (uint64_t)stride * kPer, G.nvox);   // pv >= pend: an empty run
           const uint64_t row = v / (uint64_t)nx;
           i = (int)(v - row * (uint64_t)nx);
           j = (int)(row % (uint64_t)ny);
           k = (int)(row / (uint64_t)ny);
-          yw = fmaf((float)j, G.dy, G.y0);
-          zw = fmaf((float)k, G.dz, G.z0);
-          start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, h, c0c3, cdsq, R2c, N,
+          yw = fmaf((float)j, dy, y0);
+          zw = fmaf((float)k, dz, z0);
+          start_voxel<AXIS, STICKY>(G.P, fmaf((float)i, dx, x0), yw, zw, h, cf, c0c3, cdsq, R2c, N,
                                     n_is_1, trip, z, q, dl);
         }
         const uint32_t cnt = (uint32_t)__popcll(idle);
         next_r += cnt < avail ? cnt : avail;
         if (next_r >= kChunk) have_chunk = false;
-        idle = __builtin_amdgcn_ballot_w64(v >= vend);
+        idle = __builtin_amdgcn_ballot_w64(pv >= pend);
       }
       // lanes left without a run sit on NaN (never escapes) with a far deadline
-      if (v >= vend) {
+      if (pv >= pend) {
         z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
         q = kNaN;
         dl = trip + kIdleAhead;
       }
-      if (exhausted && !__builtin_amdgcn_ballot_w64(v < vend)) break;
+      if (exhausted && !__builtin_amdgcn_ballot_w64(pv < pend)) break;
     }
   }
   if (EXTRA && G.iters) wave_add_u64(G.iters, it_lane);
