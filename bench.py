@@ -46,7 +46,7 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "7bf548b48d221c57eed08c694bbe0e62786dfd51f72c71134aa4794d7f4d63ce",
+        "sources_sha256": "8077420c347b05da9ec6db39a59f36f0ba9c57de9d1cdd157e68ade6cb5f0cac",
         "fetch_kib": 69.21, "fetch_factor": 2.0, "write_kib": 37560.08, "write_factor": 1.0,
     },
     "voxel": {
@@ -55,8 +55,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "18b969c5b47639b554d6eb4a02d61059f019e829e3820e515e09914a8cb81ade",
-        "fetch_kib": 1426.02, "fetch_factor": 2.0, "write_kib": 3026410.22, "write_factor": 1.0,
+        "sources_sha256": "305adc54a5a0f77cf103d400b060c604573f03f2b12e2bdaf276012e425ba648",
+        "fetch_kib": 1535.69, "fetch_factor": 2.0, "write_kib": 2789619.70, "write_factor": 1.0,
     },
 }
 
