@@ -447,6 +447,63 @@ def bench_de(args, dqj, workloads, torch):
     return line
 
 
+def bench_project(args, dqj, workloads, torch):
+    """Projection ("shadow") rendering: three 512x512 frames of the paper's constants,
+    each point's fibre sampled by 16 offsets (one dqj_render per frame, the
+    one-thread-per-pixel projection kernel), against the FP64 oracle's count of the
+    updates that render runs (tests/golden/ialg_project_512.json)."""
+    ps = workloads.project_512()
+    with open(os.path.join(ROOT, "tests", "golden", "ialg_project_512.json")) as f:
+        ialg = json.load(f)["total_iters"]
+    stream = torch.cuda.current_stream()
+    outs = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
+    for p, o in zip(ps, outs):
+        dqj.render(p, out=o, stream=stream)
+    torch.cuda.synchronize()
+    counted = sum(int(o["iters"].item()) for o in outs)
+    timed = [{k: v for k, v in o.items() if k != "iters"} for o in outs]
+
+    def step():
+        for p, o in zip(ps, timed):
+            dqj.render(p, out=o, stream=stream)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    achieved = FLOPS_PER_UPDATE * ialg / (ev_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": ialg / (ms * 1e-3), "unit": "Julia iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "project_512: 3 frames of 512x512, the shadows of the sets of "
+                               "the paper's constants PAPER_C[7], [0], [4] (max_iter 15, 256 "
+                               "march steps, 10 bisection steps), each fibre sampled by 16 "
+                               "offsets; one dqj_render per frame",
+                   "frames": 3, "width": 512, "height": 512, "max_iter": 15, "fibers": 16},
+        "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "render_project_kernel", "kernel_ms_per_step": ev_ms,
+                     "flops_per_update": FLOPS_PER_UPDATE,
+                     "frac_of_measured_fmac_issue": achieved / FP32_FMAC_ISSUE_TFLOPS},
+        "ialg_per_step": ialg, "ialg_source": "FP64 oracle, tests/golden/ialg_project_512.json",
+        "gpu_counted_iters_per_step": counted,
+        "hits_per_frame": [int(o["mask"].sum().item()) for o in outs],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
+    return line
+
+
 def bench_voxel(args, dqj, workloads, torch):
     """Dense voxel-grid classification (dqj_classify_grid): the 1024^3 voxel centres of
     the box for the paper's high-detail constant (max_iter 15), against the FP64 oracle's
@@ -539,7 +596,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--capacity-requests", type=int, default=300)
     ap.add_argument("--workload", choices=["plain_1024", "split_1080p", "sweep_256", "de_1024",
-                                           "voxel_1024"],
+                                           "voxel_1024", "project_512"],
                     default="plain_1024")
     ap.add_argument("--error-pixels", type=int, default=4000)
     ap.add_argument("--sweep-frames", type=int, default=4096)
@@ -569,7 +626,7 @@ def main():
     if args.workload != "plain_1024":
         torch.cuda.set_device(0)
         fn = {"split_1080p": bench_split, "sweep_256": bench_sweep, "de_1024": bench_de,
-              "voxel_1024": bench_voxel}[args.workload]
+              "voxel_1024": bench_voxel, "project_512": bench_project}[args.workload]
         print(json.dumps(fn(args, dqj, workloads, torch)), flush=True)
         return
 

@@ -117,6 +117,17 @@ typedef struct dqj_params {
    * radius about the world origin as well as to the box, so rays that miss it are
    * discarded before any update. 0 disables the sphere. */
   double cull_radius;          /* >= 0 */
+  /* Projection ("shadow") rendering, the second dimension reduction of paragraph
+   * "Dimension Reduction": with fiber_count = F > 0, a world point x is inside when any of
+   * the F points O + x U + y V + z W + fiber[f] is inside (f = 0..F-1; fiber holds F
+   * offsets in R^8, row-major F x 8, host memory read during the call). The offsets
+   * sample the directions the projection collapses, so the image is the shadow of the
+   * set sampled at those fibre points. The potential of the normal is the least of the F
+   * points' potentials. dqj_render only, FP32 fixed-step march with the dual square;
+   * other calls and modes return DQJ_E_UNSUPPORTED. 0: slice rendering. */
+  int32_t fiber_count;         /* 0..32 */
+  int32_t fiber_reserved;      /* 0 */
+  const double *fiber;         /* fiber_count x 8 values; NULL when fiber_count = 0 */
 } dqj_params;
 
 enum { DQJ_MARCH_FIXED = 0, DQJ_MARCH_DE = 1 };

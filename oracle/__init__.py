@@ -52,6 +52,9 @@ class _Params(C.Structure):
         ("k_specular", C.c_double),
         ("shininess", C.c_double),
         ("cull_radius", C.c_double),
+        ("fiber_count", C.c_int32),
+        ("fiber_reserved", C.c_int32),
+        ("fiber", C.POINTER(C.c_double)),
     ]
 
 
@@ -130,6 +133,13 @@ def make_params(p) -> _Params:
     s.k_specular = getattr(p, "k_specular", 0.0)
     s.shininess = getattr(p, "shininess", 16.0)
     s.cull_radius = getattr(p, "cull_radius", 0.0)
+    fib = getattr(p, "fiber", None)
+    if fib is not None and len(fib):
+        # the array must be C-contiguous float64 and outlive the call (the Params
+        # object holds it)
+        assert isinstance(fib, np.ndarray) and fib.dtype == np.float64 and fib.flags.c_contiguous
+        s.fiber_count = int(fib.shape[0])
+        s.fiber = fib.ctypes.data_as(C.POINTER(C.c_double))
     return s
 
 

@@ -265,23 +265,54 @@ int32_t dqjo_ray(const dqjo_params *p, int32_t i, int32_t j, double o[3], double
   return 1;
 }
 
+// Paragraph "Dimension Reduction", approach (2): the projection of the set onto the
+// 3D space of the slice. A world point of the projection is inside when some point of
+// R^8 that projects onto it is inside; the fibre of points over x is sampled by the F
+// offsets p->fiber, tried in order until one is inside. *m is the number of updates
+// spent over the points tried (N for the inside one).
 static int32_t classify_world(const dqjo_params *p, const double x[3], int32_t *m) {
   double z0[8];
   dqjo_slice_map(p, x, z0);
-  return dqjo_classify(p, z0, m, nullptr, nullptr);
+  if (p->fiber_count <= 0) return dqjo_classify(p, z0, m, nullptr, nullptr);
+  int32_t total = 0;
+  for (int32_t f = 0; f < p->fiber_count; ++f) {
+    double z[8];
+    for (int q = 0; q < 8; ++q) z[q] = z0[q] + p->fiber[8 * f + q];
+    int32_t mf;
+    const int32_t in = dqjo_classify(p, z, &mf, nullptr, nullptr);
+    total += mf;
+    if (in) {
+      *m = total;
+      return 1;
+    }
+  }
+  *m = total;
+  return 0;
 }
 
 // Normals (section "Lighting/Illumination" samples neighbouring points with a small
 // delta). The sampled field is the smooth escape potential ln||z_m||^2 / 2^m, which
 // is continuous across escape-index changes (and equals 2 ln|x| exactly for c = 0).
+// For a projection the field is the least potential over the fibre points (the
+// potential of the union of the fibre's inside sets), and *m the updates over all F.
 double dqjo_potential(const dqjo_params *p, const double x[3], int32_t *m) {
-  double z0[8], zf[8], n2;
-  int32_t mi;
+  double z0[8];
   dqjo_slice_map(p, x, z0);
-  dqjo_classify(p, z0, &mi, zf, &n2);
-  if (m) *m = mi;
-  const double v = n2 > 1e-30 ? n2 : 1e-30;
-  return log(v) * ldexp(1.0, -mi);
+  const int32_t F = p->fiber_count > 0 ? p->fiber_count : 1;
+  double best = 0.0;
+  int32_t total = 0;
+  for (int32_t f = 0; f < F; ++f) {
+    double z[8], zf[8], n2;
+    for (int q = 0; q < 8; ++q) z[q] = z0[q] + (p->fiber_count > 0 ? p->fiber[8 * f + q] : 0.0);
+    int32_t mi;
+    dqjo_classify(p, z, &mi, zf, &n2);
+    total += mi;
+    const double v = n2 > 1e-30 ? n2 : 1e-30;
+    const double G = log(v) * ldexp(1.0, -mi);
+    if (f == 0 || G < best) best = G;
+  }
+  if (m) *m = total;
+  return best;
 }
 
 struct PixelResult {

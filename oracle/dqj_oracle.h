@@ -58,6 +58,9 @@ typedef struct dqjo_params {
   int32_t normal_mode;         /* 0: potential gradient, 1: four neighbouring pixels */
   double k_specular, shininess;    /* specular term of Eq. phong */
   double cull_radius;          /* bounding sphere about the origin, 0: none */
+  int32_t fiber_count;         /* projection: 0 (slice), or F fibre offsets */
+  int32_t fiber_reserved;
+  const double *fiber;         /* F x 8 offsets in R^8 added to the slice point */
 } dqjo_params;
 
 /* ---- algebra (Appendix) ---- */

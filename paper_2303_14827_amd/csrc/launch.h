@@ -25,6 +25,16 @@ hipError_t launch_render_de(const KParams &P, const KOut &out, int waves_per_blo
 hipError_t launch_render_de_batch(const FrameDesc *table_dev, int nframes, int max_w, int max_h,
                                   int norm, bool all_axis, hipStream_t s);
 
+// Projection ("shadow") rendering: fibre offsets in R^8 added to every slice point (FP32,
+// passed by value as a kernel argument), and the one-thread-per-pixel FP32 render of the
+// projection with F of them.
+constexpr int kMaxFiber = 32;
+struct FiberTable {
+  float off[kMaxFiber][8];
+};
+hipError_t launch_render_project(const KParams &P, const FiberTable &fb, int F, const KOut &out,
+                                 hipStream_t s);
+
 // Four-neighbour normal and shade of every hit pixel of a rendered frame, from its depths.
 hipError_t launch_neighbour_normal(const KParams &P, const KOut &out, hipStream_t s);
 

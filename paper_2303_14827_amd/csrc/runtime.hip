@@ -143,6 +143,14 @@ dqj_status validate_params(const dqj_params *p) {
     return fail(DQJ_E_INVALID, "shininess must be in [1, 1e4]");
   if (!fin(p->cull_radius) || !(p->cull_radius >= 0.0))
     return fail(DQJ_E_INVALID, "cull_radius must be finite and >= 0");
+  if (p->fiber_count < 0 || p->fiber_count > kMaxFiber)
+    return fail(DQJ_E_INVALID, "fiber_count must be in 0..%d (got %d)", kMaxFiber, p->fiber_count);
+  if (p->fiber_reserved != 0) return fail(DQJ_E_INVALID, "fiber_reserved must be 0");
+  if (p->fiber_count > 0) {
+    if (!p->fiber) return fail(DQJ_E_INVALID, "fiber is NULL with fiber_count %d", p->fiber_count);
+    for (int i = 0; i < 8 * p->fiber_count; ++i)
+      if (!fin(p->fiber[i])) return fail(DQJ_E_INVALID, "fiber[%d] is not finite", i);
+  }
   if (p->precision == DQJ_PREC_SPLIT && (p->fp64_window < 1 || p->fp64_window > 8))
     return fail(DQJ_E_INVALID, "fp64_window must be in 1..8 for split precision");
   if (p->precision == DQJ_PREC_SPLIT && !(p->escape_radius * p->escape_radius < 65504.0))
@@ -165,6 +173,11 @@ dqj_status validate_params(const dqj_params *p) {
 dqj_status check_render_modes(const dqj_params &p, bool single) {
   if (p.algebra != DQJ_ALGEBRA_DUAL)
     return fail(DQJ_E_UNSUPPORTED, "the component-wise algebra is offered by dqj_classify_grid only");
+  if (p.fiber_count > 0) {
+    if (!single) return fail(DQJ_E_UNSUPPORTED, "projection rendering is offered by dqj_render only");
+    if (p.precision != DQJ_PREC_FP32 || p.march != DQJ_MARCH_FIXED)
+      return fail(DQJ_E_UNSUPPORTED, "projection rendering runs the FP32 fixed-step march");
+  }
   if (p.normal_mode == DQJ_NORMAL_NEIGHBOUR4 && !single)
     return fail(DQJ_E_UNSUPPORTED, "the four-neighbour normal is offered by dqj_render only");
   return DQJ_OK;
@@ -486,6 +499,16 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
   }
   if (sched && sched->kernel == DQJ_KERNEL_LOCKSTEP)
     return fail(DQJ_E_UNSUPPORTED, "the lock-step kernel runs the distance-estimate march only");
+  if (params->fiber_count > 0) {
+    FiberTable fb;
+    memset(&fb, 0, sizeof fb);
+    for (int f = 0; f < params->fiber_count; ++f)
+      for (int q = 0; q < 8; ++q) fb.off[f][q] = (float)params->fiber[8 * f + q];
+    e = launch_render_project(kp, fb, params->fiber_count, ko, stream);
+    if (e == hipSuccess && kp.normal_mode != 0) e = launch_neighbour_normal(kp, ko, stream);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return DQJ_OK;
+  }
   switch (params->precision) {
     case DQJ_PREC_FP32:
       e = launch_render_fp32(kp, ko, pick_schedule(sched, *params, cus), cus, stream);

@@ -14,7 +14,13 @@ ialg_voxel_1024.json: for the 1024^3 voxel grid (c from seed 0, max_iter 24, ide
 slice), the updates classification runs (escape index, or max_iter inside, summed over
 voxels) and the number of inside voxels.
 
-Run:  python tests/golden/make_golden.py [plain|de|voxel]
+ialg_project_512.json: for the three 512x512 projections (shadows) of the paper's
+constants PAPER_C[7], [0], [4] (max_iter 15, 256 march steps, 10 bisection steps, 16
+fibre offsets each), the updates the projection render runs: each march and bisection
+sample tries its fibre points in order until one is inside; each of the 6 normal samples
+runs all 16.
+
+Run:  python tests/golden/make_golden.py [plain|de|voxel|project]
 """
 import json
 import os
@@ -50,9 +56,28 @@ def _slab(nx, ny, k0, k1):
     return np.arange(k0 * nx * ny, k1 * nx * ny, dtype=np.int64)
 
 
+def project():
+    t = time.time()
+    frames = []
+    for f, (ci, p) in enumerate(zip(workloads.PROJECT_C, workloads.project_512())):
+        r = oracle.render(p)
+        frames.append({"paper_c": ci, "c": p.c, "fibers": int(p.fiber.shape[0]),
+                       "iters": r["total_iters"], "hits": int(r["mask"].sum())})
+        print(frames[-1], flush=True)
+    out = {"workload": "project_512", "width": 512, "height": 512, "max_iter": 15,
+           "march_steps": 256, "bisect_steps": 10, "frames": frames,
+           "total_iters": sum(f["iters"] for f in frames),
+           "generator": "tests/golden/make_golden.py (FP64 oracle)",
+           "oracle_seconds": round(time.time() - t, 1)}
+    with open(os.path.join(HERE, "ialg_project_512.json"), "w") as fo:
+        json.dump(out, fo, indent=1)
+
+
 def main(which):
     if which == "voxel":
         return voxel()
+    if which == "project":
+        return project()
     frames = []
     t = time.time()
     ps = workloads.plain_1024() if which == "plain" else workloads.de_1024()

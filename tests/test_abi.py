@@ -109,3 +109,27 @@ def test_batch_validation():
     assert st in (dqj.E_INVALID, dqj.E_UNSUPPORTED, dqj.E_DEVICE)
     assert dqj.lib().dqj_render_batch(arr_p, arr_o, 0, None) in (dqj.E_INVALID, dqj.E_UNSUPPORTED,
                                                                  dqj.E_DEVICE)
+
+
+def test_projection_validation():
+    """Fibre tables are checked before any device work: count 0..32, a table when the
+    count is positive, finite offsets; projection runs the FP32 fixed-step march only."""
+    import numpy as np
+    fib = np.zeros((33, 8))
+    st, msg = _render_status(BASE.replace(fiber=fib))
+    assert st == dqj.E_INVALID and "fiber_count" in msg, msg
+    bad = np.zeros((2, 8))
+    bad[1, 5] = float("nan")
+    st, msg = _render_status(BASE.replace(fiber=bad))
+    assert st == dqj.E_INVALID and "fiber" in msg, msg
+    sp = dqj.make_params(BASE)
+    sp.fiber_count = 3          # with no table
+    fo = dqj.dqj_frame_out()
+    fo.struct_size = C.sizeof(dqj.dqj_frame_out)
+    fo.mask = fo.depth = fo.shade = 0x1000
+    assert dqj.lib().dqj_render(C.byref(sp), C.byref(fo), None) == dqj.E_INVALID
+    ok = np.zeros((4, 8))
+    for kw in (dict(march=workloads.MARCH_DE), dict(precision=workloads.PREC_FP64),
+               dict(precision=workloads.PREC_SPLIT)):
+        st, msg = _render_status(BASE.replace(fiber=ok, **kw))
+        assert st == dqj.E_UNSUPPORTED and "projection" in msg, (kw, st, msg)

@@ -222,3 +222,55 @@ def test_neighbour_normal_on_the_ball(oracle_mod):
     rs = oracle_mod.render(p, pixels=pix)
     np.testing.assert_array_equal(rs["normal"], r["normal"].reshape(-1, 3)[pix])
     np.testing.assert_array_equal(rs["shade"], r["shade"].reshape(-1)[pix])
+
+
+# ---- projection ("shadow") rendering: paragraph "Dimension Reduction", approach (2)
+
+def test_projection_with_the_zero_fibre_is_the_slice(oracle_mod):
+    p = workloads.plain_128(1)[0].replace(width=48, height=40)
+    a = oracle_mod.render(p)
+    b = oracle_mod.render(p.replace(fiber=np.zeros((1, 8))))
+    for k in ("mask", "depth", "shade", "normal", "first_hit", "iters"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_projection_grows_the_set_and_moves_hits_forward(oracle_mod):
+    p = workloads.plain_128(2)[0].replace(width=48, height=48)
+    a = oracle_mod.render(p)
+    fib = workloads.fiber_ball(6, 0.5, 7)
+    b = oracle_mod.render(p.replace(fiber=fib))
+    assert np.all(b["mask"] >= a["mask"]) and b["mask"].sum() > a["mask"].sum()
+    both = (a["mask"] == 1) & (b["mask"] == 1)
+    assert np.all(b["first_hit"][both] <= a["first_hit"][both])
+    # the order of the fibre points does not change the image
+    c = oracle_mod.render(p.replace(fiber=fib[::-1].copy()))
+    for k in ("mask", "depth", "first_hit"):
+        np.testing.assert_array_equal(b[k], c[k], err_msg=k)
+
+
+@pytest.mark.parametrize("ws", [(0.3, 0.5, -0.4), (0.62,), (0.0, 0.9)])
+def test_projection_c0_shadow_is_a_smaller_ball(oracle_mod, ws):
+    """c = 0: a point (x, y, z, w | 0) stays inside for N updates iff x^2 + y^2 + z^2 + w^2
+    <= rho^2 with rho = R^(2^-N) (the quaternion norm squares with every update). With
+    fibre offsets w e3, the shadow is the ball of radius sqrt(rho^2 - min w^2)."""
+    N, S, B = 12, 64, 8
+    rho = 4.0 ** (2.0 ** -N)
+    fib = np.zeros((len(ws), 8))
+    fib[:, 3] = ws
+    p = frame(W=32, H=32, N=N, S=S, B=B, fiber=fib)
+    wmin = min(abs(w) for w in p.fiber[:, 3])
+    rs = math.sqrt(rho * rho - wmin * wmin)
+    r = oracle_mod.render(p)
+    hits = 0
+    for j in range(p.height):
+        for i in range(p.width):
+            hit, o, d, t0, t1 = oracle_mod.ray(p, i, j)
+            ts, chord = analytic_ball(np.asarray(o), np.asarray(d), rs)
+            if ts is None or chord < 2e-2:
+                if ts is None:
+                    assert r["mask"][j, i] == 0
+                continue
+            assert r["mask"][j, i] == 1
+            assert abs(r["depth"][j, i] - ts) <= (t1 - t0) / S * 2.0 ** -B + 1e-9
+            hits += 1
+    assert hits > 50

@@ -112,6 +112,7 @@ class Params:
     k_specular: float = 0.0
     shininess: float = 16.0
     cull_radius: float = 0.0
+    fiber: Optional[np.ndarray] = None   # projection: F x 8 offsets in R^8 (None: slice)
 
     def __post_init__(self):
         self.c = f32v(self.c)
@@ -134,6 +135,9 @@ class Params:
         self.k_specular = f32(self.k_specular)
         self.shininess = f32(self.shininess)
         self.cull_radius = f32(self.cull_radius)
+        if self.fiber is not None:
+            a = np.asarray(self.fiber, dtype=np.float64).reshape(-1, 8)
+            self.fiber = np.ascontiguousarray(a.astype(np.float32).astype(np.float64))
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -278,6 +282,40 @@ def de_1024(seeds: Sequence[int] = (0, 1, 2)) -> List[Params]:
     return [p.replace(march=MARCH_DE) for p in plain_1024(seeds)]
 
 
+def fiber_ball(count: int, radius: float, seed: int) -> np.ndarray:
+    """count offsets in R^8 for a projection of the identity slice: the zero offset, then
+    seeded points uniform in the ball of the given radius in the five collapsed
+    coordinates (a3 and b0..b3)."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((count, 8))
+    for f in range(1, count):
+        while True:
+            v = rng.uniform(-radius, radius, 5)
+            if float(v @ v) <= radius * radius:
+                break
+        out[f, 3:] = v
+    return out
+
+
+def project_128(seed: int = 0, fibers: int = 8) -> List[Params]:
+    """A projection (section "Dimension Reduction", approach 2) of plain_128's set: the
+    shadow of the set on the identity slice's 3D space, its fibre sampled by `fibers`
+    offsets (the zero offset and points of the 5-ball of radius 0.5)."""
+    return [p.replace(fiber=fiber_ball(fibers, 0.5, 100 + seed)) for p in plain_128(seed)]
+
+
+PROJECT_C = (7, 0, 4)   # the paper's printed constants whose sets fill the view
+
+
+def project_512(fibers: int = 16) -> List[Params]:
+    """Three 512x512 shadows of sets of the paper's printed constants (PAPER_C[7], [0],
+    [4]; max_iter 15, 256 march steps, 10 bisection steps), each fibre sampled by 16
+    offsets (zero and 15 points of the 5-ball of radius 0.5)."""
+    return [Params(c=list(PAPER_C[ci]), width=512, height=512, max_iter=15, march_steps=256,
+                   bisect_steps=10, fiber=fiber_ball(fibers, 0.5, 100 + f))
+            for f, ci in enumerate(PROJECT_C)]
+
+
 def scene_extent(p: Params) -> float:
     """Length of the box diagonal: the scale the depth tolerance is quoted in."""
     return math.sqrt(sum((b - a) ** 2 for a, b in zip(p.box_min, p.box_max)))
@@ -292,4 +330,6 @@ WORKLOADS = {
     "voxel_1024": voxel_1024,
     "split_1080p": split_1080p,
     "sweep_256": sweep_256,
+    "project_128": project_128,
+    "project_512": project_512,
 }
