@@ -23,18 +23,35 @@ struct QC {
 };
 
 // Escape index of zeta_0 = z (0 when it stays inside for N updates), with the q-form
-// update; *n2 receives ||z_m||^2 (||z_N||^2 when inside).
+// update; *n2 receives ||z_m||^2 (||z_N||^2 when inside). Two updates per loop trip, each
+// tested: the per-lane loop's control (exit mask, counter, branch) is paid once per two
+// updates. A point escaping on the first of the pair has its index and norm from that
+// update; the second runs on the escaped state (a norm of at most about R^4) and is
+// discarded.
 template <int NORM>
 __device__ __forceinline__ int classify_q(DQ<float> z, const QC &K, int N, float *n2) {
   float q = q_of(z, K.h[0]);
   float m2 = 0.0f;
   int n = 1;
-  for (; n <= N; ++n) {
+  for (; n + 1 <= N; n += 2) {
+    const float a = dq_update_q<NORM>(z, q, K.h);
+    const float b = dq_update_q<NORM>(z, q, K.h);
+    const bool ea = a > K.R2c;
+    if (ea || b > K.R2c) {
+      *n2 = (ea ? a : b) + K.h[0];
+      return ea ? n : n + 1;
+    }
+    m2 = b;
+  }
+  if (n == N) {   // odd N: the last update alone
     m2 = dq_update_q<NORM>(z, q, K.h);
-    if (m2 > K.R2c) break;
+    if (m2 > K.R2c) {
+      *n2 = m2 + K.h[0];
+      return n;
+    }
   }
   *n2 = m2 + K.h[0];
-  return n <= N ? n : 0;
+  return 0;
 }
 
 // 1 when some fibre point over world point (x, y, w) is inside; counts the updates.
