@@ -47,7 +47,8 @@ def compare(p, gpu: Dict[str, np.ndarray], ora: Dict[str, np.ndarray],
     gm = g["mask"].astype(bool)
     om = o["mask"].astype(bool)
     both_hit = gm & om
-    ddepth = np.where(both_hit, np.abs(g["depth"].astype(np.float64) - o["depth"]), 0.0)
+    with np.errstate(invalid="ignore"):   # misses carry +inf depths on both sides
+        ddepth = np.where(both_hit, np.abs(g["depth"].astype(np.float64) - o["depth"]), 0.0)
     agree = (~gm & ~om) | (both_hit & (ddepth <= tol))
     mism = np.nonzero(~agree)[0]
     rep = {
