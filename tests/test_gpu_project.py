@@ -128,3 +128,24 @@ def test_project_512_sampled(dqj, oracle_mod):
         say("frame", f, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
         assert rep["hits_oracle"] > 200
         assert_parity(rep, *BAR)
+
+
+@pytest.mark.parametrize("variant", ["realpart", "dual_slice"])
+def test_projection_variants(dqj, oracle_mod, variant):
+    """The real-part escape norm, and a slice through the dual scalar axis (W = e4) whose
+    fibre offsets lie in other directions (a3, b1, b2)."""
+    p = workloads.project_128(2)[0]
+    if variant == "realpart":
+        p = p.replace(norm=workloads.NORM_REALPART)
+    else:
+        axes = [[1.0, 0, 0, 0, 0, 0, 0, 0], [0, 1.0, 0, 0, 0, 0, 0, 0], [0, 0, 0, 0, 1.0, 0, 0, 0]]
+        fib = np.zeros((6, 8))
+        rng = np.random.default_rng(11)
+        fib[1:, [3, 5, 6]] = rng.uniform(-0.4, 0.4, (5, 3))
+        p = p.replace(slice_axes=axes, fiber=fib)
+    g = render_np(dqj, p)
+    o = oracle_mod.render(p)
+    rep = compare(p, g, o)
+    say(variant, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+    assert_parity(rep, *BAR)
+    assert abs(int(g["iters"][0]) - o["total_iters"]) <= 1e-3 * o["total_iters"]
