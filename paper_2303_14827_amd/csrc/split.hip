@@ -302,13 +302,16 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
     // unless it holds the last sample; a pair that holds the last sample, or one that
     // reached max_iter with an inside sample, ends the march (slow path, run first:
     // it leaves the lanes it ends idle, with m2 = 0, so they fail the fast test).
-    // Both tests are one select and one compare each (kp is integer-valued, so
-    // kp > S - 2 is kp - (S - 1.5) >= 0): no scalar mask arithmetic on the hot path.
+    // The three per-lane tests (both samples out, the pair holds the last sample --
+    // kp is integer-valued, so kp > S - 2 is kp >= S - 1.5 --, the deadline has come) are
+    // combined as lane masks in scalar registers; left to itself the compiler turns the
+    // combination into per-lane selects.
     const _Float16 mn = min_halves(m2);
     const bool both = mn > R2;
-    const float kq = kp - Sf2h;
-    const float xs = both ? kq : (float)(int)(trip - dl);
-    if (xs >= 0.0f) {
+    const uint64_t both_m = __builtin_amdgcn_ballot_w64(both);
+    const uint64_t last_m = __builtin_amdgcn_ballot_w64(kp >= Sf2h);
+    const uint64_t due_m = __builtin_amdgcn_ballot_w64((int)(trip - dl) >= 0);
+    if (__builtin_amdgcn_inverse_ballot_w64((both_m & last_m) | (due_m & ~both_m))) {
       const bool esc_lo = m2.x > R2;
       if (both) {
         if (COUNT) it_lane += cnt_lo + cnt_hi;
@@ -325,8 +328,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
       dl = trip + kIdleAhead;
     }
     // (the pair's test from before the slow path: the lanes it ended fail it too)
-    const float xf = both ? kq : 1.0f;
-    if (xf < 0.0f) {
+    if (__builtin_amdgcn_inverse_ballot_w64(both_m & ~last_m)) {
       if (COUNT) it_lane += cnt_lo + cnt_hi;
       kp += 2.0f;
       // The high half of the last pair lies past sample S when S is even. Without
