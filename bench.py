@@ -46,7 +46,7 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "0fbf92fd90d847ca4827f45a45d38ccdd4c94c305e1931037c4273d1b96dd7ee",
+        "sources_sha256": "28ed0229b0248677c105bfd3740ce7852c54da6f0066611e8a2feb47a4a47847",
         "fetch_kib": 69.21, "fetch_factor": 2.0, "write_kib": 37560.08, "write_factor": 1.0,
     },
     "voxel": {
@@ -55,7 +55,7 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "4f8298fff469b4892d1068784c7293300d42846c677438457b61036672286769",
+        "sources_sha256": "66fdc1be5fcb0d86dba77ac9b17c83b9435e00e66e22fa72157636dc2838838f",
         "fetch_kib": 1535.69, "fetch_factor": 2.0, "write_kib": 2789619.70, "write_factor": 1.0,
     },
 }

@@ -156,7 +156,10 @@ typedef struct dqj_frame_out {
 } dqj_frame_out;
 
 /* Render one frame (section "Ray-Marching" through "Lighting/Illumination").
- * precision FP32 and SPLIT are offered. */
+ * precision FP32 and SPLIT are offered (FP64 through SPLIT's re-bisection only); the
+ * fixed-step or distance-estimate march; slice rendering, or a projection when
+ * params->fiber_count > 0 (paragraph "Dimension Reduction"). Stream-ordered: returns after
+ * validation and the launch; errors of the kernels surface as DQJ_E_DEVICE later. */
 dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *hip_stream);
 
 /* Render n frames (params[i] -> outs[i]) in one persistent launch over a global
