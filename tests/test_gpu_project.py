@@ -149,3 +149,26 @@ def test_projection_variants(dqj, oracle_mod, variant):
     say(variant, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
     assert_parity(rep, *BAR)
     assert abs(int(g["iters"][0]) - o["total_iters"]) <= 1e-3 * o["total_iters"]
+
+
+@pytest.mark.parametrize("case", ["max_fibres", "N1", "N2_ragged", "one_offset"])
+def test_projection_edges(dqj, oracle_mod, case):
+    """The largest fibre table (32), max_iter 1 and 2 on a ragged frame, and a single
+    non-zero offset (the slice shifted in a collapsed direction)."""
+    p = workloads.plain_128(4)[0]
+    if case == "max_fibres":
+        p = p.replace(width=64, height=64, fiber=workloads.fiber_ball(32, 0.5, 3))
+    elif case == "N1":
+        p = p.replace(width=67, height=45, max_iter=1, fiber=workloads.fiber_ball(5, 0.4, 4))
+    elif case == "N2_ragged":
+        p = p.replace(width=67, height=45, max_iter=2, fiber=workloads.fiber_ball(5, 0.4, 5))
+    else:
+        fib = np.zeros((1, 8))
+        fib[0, 3] = 0.25
+        p = p.replace(fiber=fib)
+    g = render_np(dqj, p)
+    o = oracle_mod.render(p)
+    rep = compare(p, g, o)
+    say(case, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+    assert_parity(rep, *BAR)
+    assert abs(int(g["iters"][0]) - o["total_iters"]) <= 1e-3 * o["total_iters"]
