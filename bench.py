@@ -449,8 +449,8 @@ def bench_de(args, dqj, workloads, torch):
 
 def bench_project(args, dqj, workloads, torch):
     """Projection ("shadow") rendering: three 512x512 frames of the paper's constants,
-    each point's fibre sampled by 16 offsets (one dqj_render per frame, the
-    one-thread-per-pixel projection kernel), against the FP64 oracle's count of the
+    each point's fibre sampled by 16 offsets (one dqj_render per frame; the projection
+    kernel with a group of 4 lanes per pixel), against the FP64 oracle's count of the
     updates that render runs (tests/golden/ialg_project_512.json)."""
     ps = workloads.project_512()
     with open(os.path.join(ROOT, "tests", "golden", "ialg_project_512.json")) as f:

@@ -5,9 +5,16 @@
 // test is: some o_f has O + x U + y V + z W + o_f inside (N updates without escape). The
 // march, bisection and shade are those of the slice render; the potential of the normal
 // is the least potential over the F points (the potential of the union of the fibre's
-// sets). One thread per pixel: a sample costs up to F classifications and stops at the
-// first inside fibre point, and the fibre loop index is wave-uniform, so the offsets are
-// read as scalars from the kernel argument.
+// sets).
+//
+// A pixel is rendered by a group of L adjacent lanes: each sample's fibre points are
+// shared out over the group, L at a time (lane s of the group takes points s, s + L, ...),
+// and the group decides together after each round of L points. A 512 x 512 frame is
+// 262144 pixels, half of the chip's 524288 lanes at 8 waves per SIMD; with L > 1 the
+// frame fills the chip. Every decision (inside, the bisection bracket, the normal) is
+// the same as with one lane per pixel, so is the image; the count takes the points
+// in fibre order up to the first inside one, as the one-lane loop does. The offsets
+// sit in LDS, read per lane.
 #include "dq_device.h"
 #include "launch.h"
 #include "qform.h"
@@ -54,49 +61,75 @@ __device__ __forceinline__ int classify_q(DQ<float> z, const QC &K, int N, float
   return 0;
 }
 
-// 1 when some fibre point over world point (x, y, w) is inside; counts the updates.
-template <int NORM>
-__device__ __forceinline__ bool inside_union(const KParams &P, const QC &K, const FiberTable &fb, int F,
-                                             float x, float y, float w,
+// Fibre offsets of the launch, copied once per block.
+struct FiberLds {
+  float4 off[kMaxFiber][2];
+};
+
+__device__ __forceinline__ DQ<float> offset_point(const DQ<float> &z0, const FiberLds &fl, int f) {
+  const float4 lo = fl.off[f][0], hi = fl.off[f][1];
+  return DQ<float>{z0.a0 + lo.x, z0.a1 + lo.y, z0.a2 + lo.z, z0.a3 + lo.w,
+                   z0.b0 + hi.x, z0.b1 + hi.y, z0.b2 + hi.z, z0.b3 + hi.w};
+}
+
+// Bits (one per lane of this lane's group of L) of the lanes whose p holds.
+template <int L>
+__device__ __forceinline__ unsigned group_bits(bool p) {
+  const unsigned long long b = __builtin_amdgcn_ballot_w64(p);
+  return (unsigned)(b >> ((threadIdx.x & 63) & ~(L - 1))) & ((1u << L) - 1u);
+}
+
+// 1 when some fibre point over world point (x, y, w) is inside; counts the updates of
+// the points up to the first inside one in fibre order. Called by the whole group.
+template <int NORM, int L>
+__device__ __forceinline__ bool inside_union(const KParams &P, const QC &K, const FiberLds &fl, int F,
+                                             int sub, float x, float y, float w,
                                              unsigned long long &iters) {
   const DQ<float> z0 = slice_map<float>(P, x, y, w);
-  for (int f = 0; f < F; ++f) {
-    DQ<float> z{z0.a0 + fb.off[f][0], z0.a1 + fb.off[f][1], z0.a2 + fb.off[f][2],
-                z0.a3 + fb.off[f][3], z0.b0 + fb.off[f][4], z0.b1 + fb.off[f][5],
-                z0.b2 + fb.off[f][6], z0.b3 + fb.off[f][7]};
-    float n2;
-    const int m = classify_q<NORM>(z, K, P.N, &n2);
-    iters += m ? m : P.N;
-    if (m == 0) return true;
+  for (int f0 = 0; f0 < F; f0 += L) {
+    const int f = f0 + sub;
+    int m = -1;   // -1: no point for this lane in the last round
+    if (f < F) {
+      float n2;
+      m = classify_q<NORM>(offset_point(z0, fl, f), K, P.N, &n2);
+    }
+    const unsigned in = group_bits<L>(m == 0);
+    const int first = in ? __builtin_ctz(in) : L;
+    if (m >= 0 && sub <= first) iters += m ? m : P.N;
+    if (in) return true;
   }
   return false;
 }
 
-// Least escape potential over the fibre points of world point (x, y, w).
-template <int NORM>
-__device__ __forceinline__ float potential_union(const KParams &P, const QC &K, const FiberTable &fb,
-                                                 int F,
+// Least escape potential over the fibre points of world point (x, y, w), on every lane
+// of the group.
+template <int NORM, int L>
+__device__ __forceinline__ float potential_union(const KParams &P, const QC &K, const FiberLds &fl,
+                                                 int F, int sub,
                                                  float x, float y, float w,
                                                  unsigned long long &iters) {
   const DQ<float> z0 = slice_map<float>(P, x, y, w);
-  float best = 0.0f;
-  for (int f = 0; f < F; ++f) {
-    DQ<float> z{z0.a0 + fb.off[f][0], z0.a1 + fb.off[f][1], z0.a2 + fb.off[f][2],
-                z0.a3 + fb.off[f][3], z0.b0 + fb.off[f][4], z0.b1 + fb.off[f][5],
-                z0.b2 + fb.off[f][6], z0.b3 + fb.off[f][7]};
+  float best = __builtin_huge_valf();
+  for (int f = sub; f < F; f += L) {
     float n2;
-    int m = classify_q<NORM>(z, K, P.N, &n2);
+    int m = classify_q<NORM>(offset_point(z0, fl, f), K, P.N, &n2);
     m = m ? m : P.N;
     iters += m;
     const float G = potential(n2, m);
-    best = (f == 0 || G < best) ? G : best;
+    best = G < best ? G : best;
+  }
+#pragma unroll
+  for (int s = 1; s < L; s <<= 1) {
+    const float o = __shfl_xor(best, s, 64);
+    best = o < best ? o : best;
   }
   return best;
 }
 
-template <int NORM>
-__device__ void render_pixel_project(const KParams &P, const QC &K, const FiberTable &fb, int F,
-                                     int i, int j, PixelOut &r, unsigned long long &iters) {
+template <int NORM, int L>
+__device__ void render_pixel_project(const KParams &P, const QC &K, const FiberLds &fl, int F,
+                                     int sub, int i, int j, PixelOut &r,
+                                     unsigned long long &iters) {
   float d[3];
   pixel_dir(P, i, j, d);
   float t0, t1;
@@ -108,7 +141,7 @@ __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberT
   int kstar = -1;
   for (int k = 0; k <= P.S; ++k) {
     const float t = fmaf((float)k, dt, t0);
-    if (inside_union<NORM>(P, K, fb, F, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]),
+    if (inside_union<NORM, L>(P, K, fl, F, sub, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]),
                            fmaf(t, d[2], P.eye[2]), iters)) {
       kstar = k;
       break;
@@ -126,7 +159,7 @@ __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberT
     float hi = fmaf((float)kstar, dt, t0);
     for (int b = 0; b < P.B; ++b) {
       const float tm = 0.5f * (lo + hi);
-      if (inside_union<NORM>(P, K, fb, F, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]),
+      if (inside_union<NORM, L>(P, K, fl, F, sub, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]),
                              fmaf(tm, d[2], P.eye[2]), iters))
         hi = tm;
       else
@@ -142,20 +175,31 @@ __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberT
     for (int a = 0; a < 3; ++a) {
       float x[3] = {ph[0], ph[1], ph[2]};
       x[a] = ph[a] + P.h;
-      const float gp = potential_union<NORM>(P, K, fb, F, x[0], x[1], x[2], iters);
+      const float gp = potential_union<NORM, L>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
       x[a] = ph[a] - P.h;
-      const float gm = potential_union<NORM>(P, K, fb, F, x[0], x[1], x[2], iters);
+      const float gm = potential_union<NORM, L>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
       g[a] = gp - gm;
     }
   }
   finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
 }
 
-template <int NORM>
-__global__ __launch_bounds__(256) void render_project_kernel(KParams P, FiberTable fb, int F,
+template <int NORM, int L>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void render_project_kernel(KParams P, FiberTable fb, int F,
                                                              KOut out) {
-  const int i = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+  __shared__ FiberLds fl;
+  if (threadIdx.x == 0) {
+    for (int f = 0; f < F; ++f) {
+      fl.off[f][0] = make_float4(fb.off[f][0], fb.off[f][1], fb.off[f][2], fb.off[f][3]);
+      fl.off[f][1] = make_float4(fb.off[f][4], fb.off[f][5], fb.off[f][6], fb.off[f][7]);
+    }
+  }
+  __syncthreads();
+  constexpr int kRows = 16 / L;   // a block is 16 x kRows pixels
+  const int sub = threadIdx.x & (L - 1);
+  const int pix = threadIdx.x / L;
+  const int i = blockIdx.x * 16 + (pix & 15);
+  const int j = blockIdx.y * kRows + (pix >> 4);
   unsigned long long iters = 0;
   enter_update_mode();
   QC K;
@@ -165,10 +209,29 @@ __global__ __launch_bounds__(256) void render_project_kernel(KParams P, FiberTab
   K.R2c = to_vgpr(P.R2 - P.c[0]);
   if (i < P.W && j < P.H) {
     PixelOut r;
-    render_pixel_project<NORM>(P, K, fb, F, i, j, r, iters);
-    write_pixel(out, (int64_t)j * P.W + i, r);
+    render_pixel_project<NORM, L>(P, K, fl, F, sub, i, j, r, iters);
+    if (sub == 0) write_pixel(out, (int64_t)j * P.W + i, r);
   }
   if (out.iters) wave_add_u64(out.iters, iters);
+}
+
+template <int L>
+void launch_lanes(const KParams &P, const FiberTable &fb, int F, const KOut &out, hipStream_t s) {
+  const dim3 grid((P.W + 15) / 16, (P.H + 16 / L - 1) / (16 / L));
+  if (P.norm == 0)
+    hipLaunchKernelGGL((render_project_kernel<0, L>), grid, dim3(256), 0, s, P, fb, F, out);
+  else
+    hipLaunchKernelGGL((render_project_kernel<1, L>), grid, dim3(256), 0, s, P, fb, F, out);
+}
+
+// Lanes per pixel: the least of 1, 2 and 4 that puts about 2^20 lanes (twice the chip's
+// 524288 at 8 waves per SIMD) into the launch, and no more than the points of a round.
+// On a 512 x 512 frame of 16 points, 4 lanes per pixel took a frame from 3.3 to 2.5 ms;
+// on 1024 x 1024, more than one lane per pixel gained nothing or cost time.
+int project_lanes(const KParams &P, int F) {
+  int lanes = 1;
+  while (lanes < 4 && 2 * lanes <= F && (int64_t)P.W * P.H * lanes < (int64_t(1) << 20)) lanes *= 2;
+  return lanes;
 }
 
 }  // namespace
@@ -176,11 +239,11 @@ __global__ __launch_bounds__(256) void render_project_kernel(KParams P, FiberTab
 hipError_t launch_render_project(const KParams &P, const FiberTable &fb, int F, const KOut &out,
                                  hipStream_t s) {
   if (F < 1 || F > kMaxFiber) return hipErrorInvalidValue;
-  const dim3 grid((P.W + 15) / 16, (P.H + 15) / 16);
-  if (P.norm == 0)
-    hipLaunchKernelGGL(render_project_kernel<0>, grid, dim3(256), 0, s, P, fb, F, out);
-  else
-    hipLaunchKernelGGL(render_project_kernel<1>, grid, dim3(256), 0, s, P, fb, F, out);
+  switch (project_lanes(P, F)) {
+    case 1: launch_lanes<1>(P, fb, F, out, s); break;
+    case 2: launch_lanes<2>(P, fb, F, out, s); break;
+    default: launch_lanes<4>(P, fb, F, out, s); break;
+  }
   return hipGetLastError();
 }
 

@@ -172,3 +172,25 @@ def test_projection_edges(dqj, oracle_mod, case):
     say(case, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
     assert_parity(rep, *BAR)
     assert abs(int(g["iters"][0]) - o["total_iters"]) <= 1e-3 * o["total_iters"]
+
+
+@pytest.mark.parametrize("side,fibres,lanes", [(1024, 3, 1), (768, 2, 2), (128, 3, 2), (128, 8, 4)])
+def test_projection_lane_groups(dqj, oracle_mod, side, fibres, lanes):
+    """Each grouping of lanes per pixel: 1, 2 or 4, the least that gives the launch about
+    2^20 lanes, at most the fibre count (the grouping leaves the image unchanged; here each
+    one is checked against the oracle on a whole frame, with the update count)."""
+    group = 1
+    while group < 4 and 2 * group <= fibres and side * side * group < (1 << 20):
+        group *= 2
+    assert group == lanes
+    small = side <= 128
+    p = workloads.plain_128(4)[0].replace(
+        width=side, height=side, max_iter=8 if small else 4, march_steps=128 if small else 16,
+        bisect_steps=8 if small else 3, fiber=workloads.fiber_ball(fibres, 0.4, 6))
+    g = render_np(dqj, p)
+    o = oracle_mod.render(p)
+    rep = compare(p, g, o)
+    say(side, fibres, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
+    assert rep["hits_oracle"] > 100
+    assert_parity(rep, *BAR)
+    assert abs(int(g["iters"][0]) - o["total_iters"]) <= 1e-3 * o["total_iters"]
