@@ -79,9 +79,10 @@ __device__ __forceinline__ unsigned group_bits(bool p) {
   return (unsigned)(b >> ((threadIdx.x & 63) & ~(L - 1))) & ((1u << L) - 1u);
 }
 
-// 1 when some fibre point over world point (x, y, w) is inside; counts the updates of
-// the points up to the first inside one in fibre order. Called by the whole group.
-template <int NORM, int L>
+// 1 when some fibre point over world point (x, y, w) is inside; with COUNT, counts the
+// updates of the points up to the first inside one in fibre order. Called by the whole
+// group.
+template <int NORM, int L, bool COUNT>
 __device__ __forceinline__ bool inside_union(const KParams &P, const QC &K, const FiberLds &fl, int F,
                                              int sub, float x, float y, float w,
                                              unsigned long long &iters) {
@@ -94,8 +95,10 @@ __device__ __forceinline__ bool inside_union(const KParams &P, const QC &K, cons
       m = classify_q<NORM>(offset_point(z0, fl, f), K, P.N, &n2);
     }
     const unsigned in = group_bits<L>(m == 0);
-    const int first = in ? __builtin_ctz(in) : L;
-    if (m >= 0 && sub <= first) iters += m ? m : P.N;
+    if constexpr (COUNT) {
+      const int first = in ? __builtin_ctz(in) : L;
+      if (m >= 0 && sub <= first) iters += m ? m : P.N;
+    }
     if (in) return true;
   }
   return false;
@@ -103,7 +106,7 @@ __device__ __forceinline__ bool inside_union(const KParams &P, const QC &K, cons
 
 // Least escape potential over the fibre points of world point (x, y, w), on every lane
 // of the group.
-template <int NORM, int L>
+template <int NORM, int L, bool COUNT>
 __device__ __forceinline__ float potential_union(const KParams &P, const QC &K, const FiberLds &fl,
                                                  int F, int sub,
                                                  float x, float y, float w,
@@ -114,7 +117,7 @@ __device__ __forceinline__ float potential_union(const KParams &P, const QC &K, 
     float n2;
     int m = classify_q<NORM>(offset_point(z0, fl, f), K, P.N, &n2);
     m = m ? m : P.N;
-    iters += m;
+    if constexpr (COUNT) iters += m;
     const float G = potential(n2, m);
     best = G < best ? G : best;
   }
@@ -126,7 +129,7 @@ __device__ __forceinline__ float potential_union(const KParams &P, const QC &K, 
   return best;
 }
 
-template <int NORM, int L>
+template <int NORM, int L, bool COUNT>
 __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberLds &fl, int F,
                                      int sub, int i, int j, PixelOut &r,
                                      unsigned long long &iters) {
@@ -141,7 +144,7 @@ __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberL
   int kstar = -1;
   for (int k = 0; k <= P.S; ++k) {
     const float t = fmaf((float)k, dt, t0);
-    if (inside_union<NORM, L>(P, K, fl, F, sub, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]),
+    if (inside_union<NORM, L, COUNT>(P, K, fl, F, sub, fmaf(t, d[0], P.eye[0]), fmaf(t, d[1], P.eye[1]),
                            fmaf(t, d[2], P.eye[2]), iters)) {
       kstar = k;
       break;
@@ -159,7 +162,7 @@ __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberL
     float hi = fmaf((float)kstar, dt, t0);
     for (int b = 0; b < P.B; ++b) {
       const float tm = 0.5f * (lo + hi);
-      if (inside_union<NORM, L>(P, K, fl, F, sub, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]),
+      if (inside_union<NORM, L, COUNT>(P, K, fl, F, sub, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]),
                              fmaf(tm, d[2], P.eye[2]), iters))
         hi = tm;
       else
@@ -175,16 +178,16 @@ __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberL
     for (int a = 0; a < 3; ++a) {
       float x[3] = {ph[0], ph[1], ph[2]};
       x[a] = ph[a] + P.h;
-      const float gp = potential_union<NORM, L>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
+      const float gp = potential_union<NORM, L, COUNT>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
       x[a] = ph[a] - P.h;
-      const float gm = potential_union<NORM, L>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
+      const float gm = potential_union<NORM, L, COUNT>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
       g[a] = gp - gm;
     }
   }
   finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
 }
 
-template <int NORM, int L>
+template <int NORM, int L, bool COUNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void render_project_kernel(KParams P, FiberTable fb, int F,
                                                              KOut out) {
   __shared__ FiberLds fl;
@@ -209,19 +212,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void r
   K.R2c = to_vgpr(P.R2 - P.c[0]);
   if (i < P.W && j < P.H) {
     PixelOut r;
-    render_pixel_project<NORM, L>(P, K, fl, F, sub, i, j, r, iters);
+    render_pixel_project<NORM, L, COUNT>(P, K, fl, F, sub, i, j, r, iters);
     if (sub == 0) write_pixel(out, (int64_t)j * P.W + i, r);
   }
-  if (out.iters) wave_add_u64(out.iters, iters);
+  if constexpr (COUNT) wave_add_u64(out.iters, iters);
 }
 
+// The counting kernels run only where the caller asked for the update count.
 template <int L>
 void launch_lanes(const KParams &P, const FiberTable &fb, int F, const KOut &out, hipStream_t s) {
   const dim3 grid((P.W + 15) / 16, (P.H + 16 / L - 1) / (16 / L));
-  if (P.norm == 0)
-    hipLaunchKernelGGL((render_project_kernel<0, L>), grid, dim3(256), 0, s, P, fb, F, out);
-  else
-    hipLaunchKernelGGL((render_project_kernel<1, L>), grid, dim3(256), 0, s, P, fb, F, out);
+  const bool count = out.iters != nullptr;
+  if (P.norm == 0) {
+    if (count)
+      hipLaunchKernelGGL((render_project_kernel<0, L, true>), grid, dim3(256), 0, s, P, fb, F, out);
+    else
+      hipLaunchKernelGGL((render_project_kernel<0, L, false>), grid, dim3(256), 0, s, P, fb, F, out);
+  } else {
+    if (count)
+      hipLaunchKernelGGL((render_project_kernel<1, L, true>), grid, dim3(256), 0, s, P, fb, F, out);
+    else
+      hipLaunchKernelGGL((render_project_kernel<1, L, false>), grid, dim3(256), 0, s, P, fb, F, out);
+  }
 }
 
 // Lanes per pixel: the least of 1, 2 and 4 that puts about 2^20 lanes (twice the chip's

@@ -194,3 +194,21 @@ def test_projection_lane_groups(dqj, oracle_mod, side, fibres, lanes):
     assert rep["hits_oracle"] > 100
     assert_parity(rep, *BAR)
     assert abs(int(g["iters"][0]) - o["total_iters"]) <= 1e-3 * o["total_iters"]
+
+
+@pytest.mark.parametrize("side", [128, 1024])
+def test_projection_count_off_same_image(dqj, side):
+    """Without an update counter the launch takes the non-counting kernels; the image is
+    bitwise that of the counting launch (4 lanes per pixel at 128^2, one at 1024^2)."""
+    import torch
+    p = workloads.plain_128(4)[0].replace(width=side, height=side, max_iter=8, march_steps=32,
+                                          bisect_steps=4, fiber=workloads.fiber_ball(8, 0.4, 7))
+    a = dqj.alloc_outputs(side, side, extras=False)
+    b = {k: v for k, v in dqj.alloc_outputs(side, side, extras=False).items() if k != "iters"}
+    a["iters"].zero_()
+    dqj.render(p, out=a)
+    dqj.render(p, out=b)
+    torch.cuda.synchronize()
+    assert int(a["iters"].item()) > 0
+    for k in ("mask", "depth", "shade"):
+        assert torch.equal(a[k], b[k]), k
