@@ -17,7 +17,7 @@ struct KIter64 {
 hipError_t launch_render_direct(const KParams &P, const KOut &out, hipStream_t s);
 
 // Distance-estimate march in FP32: one thread per pixel, blocks of waves_per_block (1-4)
-// waves of 16 x 4 pixels each.
+// waves of 8 x 8 pixels each.
 hipError_t launch_render_de(const KParams &P, const KOut &out, int waves_per_block, hipStream_t s);
 
 // The distance-estimate march over n frames of a device table (one-thread-per-pixel kernel,
