@@ -198,11 +198,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void r
     }
   }
   __syncthreads();
-  constexpr int kRows = 16 / L;   // a block is 16 x kRows pixels
+  // Each wave renders a compact tile of 64 / L pixels (8 x 8, 8 x 4 or 4 x 4), whose rays
+  // are more alike than a row's; the block's four waves form a 2 x 2 arrangement of them.
+  constexpr int kWaveW = L == 4 ? 4 : 8, kWaveH = 64 / L / kWaveW;
   const int sub = threadIdx.x & (L - 1);
-  const int pix = threadIdx.x / L;
-  const int i = blockIdx.x * 16 + (pix & 15);
-  const int j = blockIdx.y * kRows + (pix >> 4);
+  const int wave = threadIdx.x >> 6;
+  const int pix = (threadIdx.x & 63) / L;
+  const int i = blockIdx.x * (2 * kWaveW) + (wave & 1) * kWaveW + pix % kWaveW;
+  const int j = blockIdx.y * (2 * kWaveH) + (wave >> 1) * kWaveH + pix / kWaveW;
   unsigned long long iters = 0;
   enter_update_mode();
   QC K;
@@ -221,7 +224,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void r
 // The counting kernels run only where the caller asked for the update count.
 template <int L>
 void launch_lanes(const KParams &P, const FiberTable &fb, int F, const KOut &out, hipStream_t s) {
-  const dim3 grid((P.W + 15) / 16, (P.H + 16 / L - 1) / (16 / L));
+  constexpr int kWaveW = L == 4 ? 4 : 8, kWaveH = 64 / L / kWaveW;
+  const dim3 grid((P.W + 2 * kWaveW - 1) / (2 * kWaveW), (P.H + 2 * kWaveH - 1) / (2 * kWaveH));
   const bool count = out.iters != nullptr;
   if (P.norm == 0) {
     if (count)
