@@ -243,8 +243,9 @@ void launch_lanes(const KParams &P, const FiberTable &fb, int F, const KOut &out
 // Lanes per pixel: the least of 1, 2 and 4 that puts about 2^20 lanes (twice the chip's
 // 524288 at 8 waves per SIMD) into the launch, and at most F (a larger group would leave
 // lanes without a point in every round). On a 512 x 512 frame of 16 points, 4 lanes per
-// pixel took a frame from 3.3 to 2.5 ms (2 lanes: 2.5 to 2.1 ms later, against 1.9 for
-// 4); on 1024 x 1024, more than one lane per pixel gained nothing or cost time.
+// pixel took a frame from 3.3 to 2.5 ms; with the compact wave tiles, 4 lanes take 1.9 ms
+// against 2.1 for 2. On 1024 x 1024, more than one lane per pixel gained nothing or cost
+// time.
 int project_lanes(const KParams &P, int F) {
   int lanes = 1;
   while (lanes < 4 && 2 * lanes <= F && (int64_t)P.W * P.H * lanes < (int64_t(1) << 20)) lanes *= 2;
