@@ -46,7 +46,7 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "7811b88f7636204dd39103ff6599882d51b31a21b229dcd6362f81dffaebc5ae",
+        "sources_sha256": "06c823f00aca90080aefa4b3b9c9ac73074ddf38c290ba40208b5abc8c7d8cdb",
         "fetch_kib": 69.21, "fetch_factor": 2.0, "write_kib": 37560.08, "write_factor": 1.0,
     },
     "voxel": {

@@ -78,11 +78,13 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
 hipError_t launch_de_table(const FrameDesc *dev, const std::vector<FrameDesc> &table, int norm,
                            bool all_axis, hipStream_t s) {
   int mw = 0, mh = 0;
+  bool count = false;
   for (const FrameDesc &f : table) {
     mw = f.P.W > mw ? f.P.W : mw;
     mh = f.P.H > mh ? f.P.H : mh;
+    count = count || f.out.iters != nullptr;
   }
-  return launch_render_de_batch(dev, (int)table.size(), mw, mh, norm, all_axis, s);
+  return launch_render_de_batch(dev, (int)table.size(), mw, mh, norm, all_axis, count, s);
 }
 
 // Allocations an eager batch leaves behind until the stream has passed them.

@@ -21,9 +21,10 @@ hipError_t launch_render_direct(const KParams &P, const KOut &out, hipStream_t s
 hipError_t launch_render_de(const KParams &P, const KOut &out, int waves_per_block, hipStream_t s);
 
 // The distance-estimate march over n frames of a device table (one-thread-per-pixel kernel,
-// frame = blockIdx.z); all frames share norm; all_axis: every frame on the identity slice.
+// frame = blockIdx.z); all frames share norm; all_axis: every frame on the identity slice;
+// count: some frame has an update counter (else the kernel without counting runs).
 hipError_t launch_render_de_batch(const FrameDesc *table_dev, int nframes, int max_w, int max_h,
-                                  int norm, bool all_axis, hipStream_t s);
+                                  int norm, bool all_axis, bool count, hipStream_t s);
 
 // Projection ("shadow") rendering: fibre offsets in R^8 added to every slice point (FP32,
 // passed by value as a kernel argument), and the one-thread-per-pixel FP32 render of the

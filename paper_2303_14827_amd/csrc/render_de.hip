@@ -108,7 +108,7 @@ __device__ __forceinline__ int classify_de(const KParams &P, const QConst &K, DQ
   return n;
 }
 
-template <int NORM, bool AXIS>
+template <int NORM, bool AXIS, bool COUNT>
 __device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j, PixelOut &r,
                                 unsigned long long &iters) {
   float d[3];
@@ -129,7 +129,7 @@ __device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j,
                    K.h[0], z, q);
     float de = 0.0f, n2;
     const int m = classify_de<NORM, true>(P, K, z, q, &de, &n2);
-    iters += m ? m : P.N;
+    if constexpr (COUNT) iters += m ? m : P.N;
     if (m == 0) {   // inside: the hit is t0 on the first point, else bisect the last step
       kstar = k;
       if (k > 0) {
@@ -161,7 +161,7 @@ __device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j,
       de_start<AXIS>(P, fmaf(tm, d[0], P.eye[0]), fmaf(tm, d[1], P.eye[1]), fmaf(tm, d[2], P.eye[2]),
                      K.h[0], z, q);
       const int m = classify_de<NORM, false>(P, K, z, q, &unused, &n2);
-      iters += m ? m : P.N;
+      if constexpr (COUNT) iters += m ? m : P.N;
       if (m == 0)
         hi = tm;
       else
@@ -186,7 +186,7 @@ __device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j,
       de_start<AXIS>(P, x[0], x[1], x[2], K.h[0], z, q);
       int m = classify_de<NORM, false>(P, K, z, q, &unused, &n2);
       m = m ? m : P.N;
-      iters += m;
+      if constexpr (COUNT) iters += m;
       const float G = potential(n2, m);
       gp = sgn == 0 ? G : gp - G;
     }
@@ -200,7 +200,7 @@ __device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j,
 // small blocks free slots sooner; a square wave's rays are more alike than a 16 x 4
 // stripe's (the three-frame batch of 1024^2 frames: 2.22 ms with stripes, 1.86 ms with
 // squares, the same image).
-template <int NORM, bool AXIS>
+template <int NORM, bool AXIS, bool COUNT>
 __device__ __forceinline__ void render_de_block(const KParams &P, const KOut &out) {
   const int i = blockIdx.x * 8 + (threadIdx.x & 7);
   const int j = blockIdx.y * (blockDim.x >> 3) + (threadIdx.x >> 3);
@@ -210,26 +210,30 @@ __device__ __forceinline__ void render_de_block(const KParams &P, const KOut &ou
   unsigned long long iters = 0;
   if (i < P.W && j < P.H) {
     PixelOut r;
-    render_pixel_de<NORM, AXIS>(P, K, i, j, r, iters);
+    render_pixel_de<NORM, AXIS, COUNT>(P, K, i, j, r, iters);
     write_pixel(out, (int64_t)j * P.W + i, r);
   }
-  if (out.iters) wave_add_u64(out.iters, iters);
+  if constexpr (COUNT) {
+    if (out.iters) wave_add_u64(out.iters, iters);
+  }
 }
 
-template <int NORM, bool AXIS>
+// COUNT: the launch has an update counter to fill (the other kernels compile the
+// counting out).
+template <int NORM, bool AXIS, bool COUNT>
 __global__ __launch_bounds__(256) void render_de_kernel(KParams P, KOut out) {
-  render_de_block<NORM, AXIS>(P, out);
+  render_de_block<NORM, AXIS, COUNT>(P, out);
 }
 
 // Several frames in one launch (frame = blockIdx.z, records from a device table): the
 // hardware dispatches the frames' blocks in turn, so one frame's slowest waves overlap
 // the next frame's work instead of ending a launch each.
-template <int NORM, bool AXIS>
+template <int NORM, bool AXIS, bool COUNT>
 __global__ __launch_bounds__(256) void render_de_batch_kernel(const FrameDesc *__restrict__ table) {
   const persist::ConstFrame F = (persist::ConstFrame)table + blockIdx.z;
   const KParams &P = F->P;
   if ((int)(blockIdx.x * 8) >= P.W || (int)(blockIdx.y * 8) >= P.H) return;
-  render_de_block<NORM, AXIS>(P, F->out);
+  render_de_block<NORM, AXIS, COUNT>(P, F->out);
 }
 
 }  // namespace
@@ -239,8 +243,13 @@ hipError_t launch_render_de(const KParams &P, const KOut &out, int waves_per_blo
   const int bh = 8 * wpb;
   dim3 grid((P.W + 7) / 8, (P.H + bh - 1) / bh);
   const bool axis = P.axis_slice != 0;
-#define DQJ_DE_DIRECT(NM, AX) \
-  hipLaunchKernelGGL((render_de_kernel<NM, AX>), grid, dim3(64 * wpb), 0, s, P, out)
+#define DQJ_DE_DIRECT(NM, AX)                                                               \
+  do {                                                                                      \
+    if (out.iters)                                                                          \
+      hipLaunchKernelGGL((render_de_kernel<NM, AX, true>), grid, dim3(64 * wpb), 0, s, P, out); \
+    else                                                                                    \
+      hipLaunchKernelGGL((render_de_kernel<NM, AX, false>), grid, dim3(64 * wpb), 0, s, P, out); \
+  } while (0)
   if (P.norm == 0) {
     if (axis)
       DQJ_DE_DIRECT(0, true);
@@ -257,10 +266,15 @@ hipError_t launch_render_de(const KParams &P, const KOut &out, int waves_per_blo
 }
 
 hipError_t launch_render_de_batch(const FrameDesc *table_dev, int nframes, int max_w, int max_h,
-                                  int norm, bool all_axis, hipStream_t s) {
+                                  int norm, bool all_axis, bool count, hipStream_t s) {
   const dim3 grid((max_w + 7) / 8, (max_h + 7) / 8, nframes);
-#define DQJ_DE_BATCH(NM, AX) \
-  hipLaunchKernelGGL((render_de_batch_kernel<NM, AX>), grid, dim3(64), 0, s, table_dev)
+#define DQJ_DE_BATCH(NM, AX)                                                                 \
+  do {                                                                                       \
+    if (count)                                                                               \
+      hipLaunchKernelGGL((render_de_batch_kernel<NM, AX, true>), grid, dim3(64), 0, s, table_dev); \
+    else                                                                                     \
+      hipLaunchKernelGGL((render_de_batch_kernel<NM, AX, false>), grid, dim3(64), 0, s, table_dev); \
+  } while (0)
   if (norm == 0) {
     if (all_axis)
       DQJ_DE_BATCH(0, true);

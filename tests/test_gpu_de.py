@@ -204,3 +204,28 @@ def test_de_modes_not_offered(dqj):
     with dqj.Server(precision=workloads.PREC_FP32) as srv:
         st, _ = srv.submit_status(p, dqj.alloc_outputs(128, 128, extras=False))
         assert st == dqj.E_UNSUPPORTED
+
+
+def test_de_count_off_same_image(dqj):
+    """Without an update counter, single renders and batches take the DE kernels with the
+    counting compiled out; the images are bitwise those of the counting launches."""
+    import torch
+    ps = workloads.de_128(0) + workloads.de_128(1)
+    def outs(count):
+        o = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
+        for x in o:
+            x["iters"].zero_()
+        return o if count else [{k: v for k, v in x.items() if k != "iters"} for x in o]
+    a, b = outs(True), outs(False)
+    for p, o in zip(ps, a):
+        dqj.render(p, out=o)
+    for p, o in zip(ps, b):
+        dqj.render(p, out=o)
+    ba, bb = outs(True), outs(False)
+    dqj.render_batch(ps, ba)
+    dqj.render_batch(ps, bb)
+    torch.cuda.synchronize()
+    for x, y, u, v in zip(a, b, ba, bb):
+        assert int(x["iters"].item()) > 0 and int(u["iters"].item()) == int(x["iters"].item())
+        for k in ("mask", "depth", "shade"):
+            assert torch.equal(x[k], y[k]) and torch.equal(x[k], u[k]) and torch.equal(x[k], v[k]), k
