@@ -26,6 +26,13 @@
  *
  * Readings where the paper is silent or garbled are listed in the oracle source
  * next to the code that takes them.
+ *
+ * Pins (CPU tests, independent of these formulas): algebra identities, c = 0 closed
+ * forms of the iteration, the render (ball, and the quadric of a general affine slice
+ * with its origin and axis order) and the projection (union of shifted balls, least
+ * potential over the fibre), the quaternion and complex reductions, symmetries, the
+ * dual part as a derivative, and brute-force marches. Parity unpinned: shading for
+ * c != 0 (no closed form; the GPU is checked against this oracle only).
  */
 #ifndef DQJ_ORACLE_H
 #define DQJ_ORACLE_H

@@ -290,10 +290,58 @@ def alloc_outputs(width: int, height: int, device="cuda", extras: bool = True):
     return o
 
 
-def make_frame_out(o: Dict) -> dqj_frame_out:
+# dtype and elements per pixel of each output buffer ("iters" is one counter per frame)
+_OUT_SPEC = {"mask": ("uint8", 1), "depth": ("float32", 1), "shade": ("float32", 1),
+             "image8": ("uint8", 1), "normal": ("float32", 3), "first_hit": ("int32", 1),
+             "flags": ("uint8", 1), "iters": ("int64", 0)}
+_REQUIRED_OUT = ("mask", "depth", "shade")
+
+
+def check_device_tensor(name: str, t, dtype: str, min_numel: int, where: bool = True):
+    """Raise ValueError unless t is a contiguous torch tensor of the given dtype on the
+    current GPU with at least min_numel elements. The C ABI receives raw device
+    pointers, so this is the only place a wrong buffer can be refused before a kernel
+    writes through it."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.{dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {min_numel} needed")
+    if where:
+        check_on_current_gpu(name, t)
+
+
+def check_on_current_gpu(name: str, t):
+    import torch
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: tensor is on {t.device}, not on the GPU")
+    cur = torch.cuda.current_device()
+    if t.device.index is not None and t.device.index != cur:
+        raise ValueError(f"{name}: tensor is on cuda:{t.device.index}, current device is cuda:{cur}")
+
+
+def make_frame_out(o: Dict, p=None) -> dqj_frame_out:
+    """Marshal an output dict. With the frame's parameters p, every tensor is checked
+    (device, dtype, contiguity, size) before its pointer is passed on."""
     f = dqj_frame_out()
     f.struct_size = C.sizeof(dqj_frame_out)
-    for name in ("mask", "depth", "shade", "image8", "normal", "first_hit", "flags", "iters"):
+    npix = int(p.width) * int(p.height) if p is not None else 0
+    if p is not None:   # format of every buffer first, then where each one lives
+        for name in _REQUIRED_OUT:
+            if o.get(name) is None:
+                raise ValueError(f"output '{name}' is required")
+        for name, (dtype, per_px) in _OUT_SPEC.items():
+            if o.get(name) is not None:
+                check_device_tensor(name, o[name], dtype, per_px * npix if per_px else 1,
+                                    where=False)
+        for name in _OUT_SPEC:
+            if o.get(name) is not None:
+                check_on_current_gpu(name, o[name])
+    for name in _OUT_SPEC:
         t = o.get(name)
         setattr(f, name, t.data_ptr() if t is not None else None)
     return f
@@ -312,7 +360,7 @@ def render(p, out: Optional[Dict] = None, stream=None, schedule: Optional[dqj_sc
     if out is None:
         out = alloc_outputs(p.width, p.height, extras=extras)
     sp = make_params(p)
-    fo = make_frame_out(out)
+    fo = make_frame_out(out, p)
     if schedule is None:
         _check(lib().dqj_render(C.byref(sp), C.byref(fo), _stream(stream)))
     else:
@@ -327,8 +375,10 @@ def render_batch(ps: Sequence, outs: Optional[List[Dict]] = None, stream=None,
     n = len(ps)
     if outs is None:
         outs = [alloc_outputs(p.width, p.height, extras=extras) for p in ps]
+    if len(outs) != n:
+        raise ValueError(f"{n} frames but {len(outs)} output dicts")
     arr_p = (dqj_params * n)(*[make_params(p) for p in ps])
-    arr_o = (dqj_frame_out * n)(*[make_frame_out(o) for o in outs])
+    arr_o = (dqj_frame_out * n)(*[make_frame_out(o, p) for p, o in zip(ps, outs)])
     _check(lib().dqj_render_batch(arr_p, arr_o, n, _stream(stream)))
     return outs
 
@@ -339,9 +389,11 @@ class BatchPlan:
     def __init__(self, ps: Sequence, outs: List[Dict], schedule: Optional[dqj_schedule] = None,
                  stream=None):
         n = len(ps)
+        if len(outs) != n:
+            raise ValueError(f"{n} frames but {len(outs)} output dicts")
         self.outs = outs
         arr_p = (dqj_params * n)(*[make_params(p) for p in ps])
-        arr_o = (dqj_frame_out * n)(*[make_frame_out(o) for o in outs])
+        arr_o = (dqj_frame_out * n)(*[make_frame_out(o, p) for p, o in zip(ps, outs)])
         h = C.c_void_p()
         _check(lib().dqj_batch_plan_create(arr_p, arr_o, n,
                                            C.byref(schedule) if schedule is not None else None,
@@ -366,8 +418,10 @@ class BatchPlan:
 def autotune(ps: Sequence, outs: List[Dict], cache_path: Optional[str] = None) -> dqj_schedule:
     """Pick the fastest schedule for frames like ps (renders them into outs)."""
     n = len(ps)
+    if len(outs) != n:
+        raise ValueError(f"{n} frames but {len(outs)} output dicts")
     arr_p = (dqj_params * n)(*[make_params(p) for p in ps])
-    arr_o = (dqj_frame_out * n)(*[make_frame_out(o) for o in outs])
+    arr_o = (dqj_frame_out * n)(*[make_frame_out(o, p) for p, o in zip(ps, outs)])
     best = make_schedule()
     _check(lib().dqj_autotune(arr_p, arr_o, n, cache_path.encode() if cache_path else None,
                               C.byref(best)))
@@ -377,6 +431,10 @@ def autotune(ps: Sequence, outs: List[Dict], cache_path: Optional[str] = None) -
 def classify_points(pts, p, precision: int = PREC_FP32, stream=None):
     """Classify device points (n x 8, float32 or float64). Returns (escape_iter, final_norm2)."""
     import torch
+    if pts.dim() != 2 or pts.shape[1] != 8:
+        raise ValueError(f"points: shape {tuple(pts.shape)}, expected (n, 8)")
+    check_device_tensor("points", pts, "float64" if precision == PREC_FP64 else "float32",
+                        pts.shape[0] * 8)
     n = pts.shape[0]
     esc = torch.empty((n,), dtype=torch.int32, device=pts.device)
     n2 = torch.empty((n,), dtype=torch.float32, device=pts.device)
@@ -399,6 +457,12 @@ def classify_grid(p, nx: int, ny: int, nz: int, mask=None, escape=None, iters=No
         escape = torch.empty((nz, ny, nx), dtype=torch.int32, device="cuda")
     if extras and iters is None:
         iters = torch.zeros((1,), dtype=torch.int64, device="cuda")
+    nvox = int(nx) * int(ny) * int(nz)
+    check_device_tensor("mask", mask, "uint8", nvox)
+    if escape is not None:
+        check_device_tensor("escape", escape, "int32", nvox)
+    if iters is not None:
+        check_device_tensor("iters", iters, "int64", 1)
     sp = make_params(p)
     ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
     _check(lib().dqj_classify_grid(C.byref(sp), nx, ny, nz, ptr(mask), ptr(escape), ptr(iters),
@@ -445,7 +509,7 @@ class Server:
 
     def submit(self, p, out: Dict) -> int:
         sp = make_params(p)
-        fo = make_frame_out(out)
+        fo = make_frame_out(out, p)
         t = C.c_uint64()
         _check(lib().dqj_serve_submit(self._h, C.byref(sp), C.byref(fo), C.byref(t)))
         self._keep[t.value] = out
@@ -454,7 +518,7 @@ class Server:
     def submit_status(self, p, out: Dict):
         """(status, ticket) without raising: for tests of refusals."""
         sp = make_params(p)
-        fo = make_frame_out(out)
+        fo = make_frame_out(out, p)
         t = C.c_uint64()
         st = lib().dqj_serve_submit(self._h, C.byref(sp), C.byref(fo), C.byref(t))
         if st == OK:

@@ -72,6 +72,10 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
 
   // ---- wave-uniform state
   const ConstFrame ctable = (ConstFrame)table;
+  // F is null in batch launches until the wave takes its first tile: no read through F
+  // (the frame's constants, its outputs) may happen before a tile is assigned. Every
+  // such read sits in the slow path or the hand-out below, which only lanes with a ray
+  // reach; a read hoisted to the top of the trip dereferences a null pointer.
   typename FramePtr<BATCH>::type F;
   if constexpr (BATCH)
     F = nullptr;

@@ -10,9 +10,9 @@ ialg_de_1024.json: the same for the same three frames marched by distance estima
 (at most 512 steps, hit below 1e-4, steps clamped to [1e-4, 0.25], 10 bisection steps
 when a step lands inside).
 
-ialg_voxel_1024.json: for the 1024^3 voxel grid (c from seed 0, max_iter 24, identity
-slice), the updates classification runs (escape index, or max_iter inside, summed over
-voxels) and the number of inside voxels.
+ialg_voxel_1024.json: for the 1024^3 voxel grid (the paper's high-detail constant
+PAPER_C[7] with its max_iter 15, identity slice), the updates classification runs
+(escape index, or max_iter inside, summed over voxels) and the number of inside voxels.
 
 ialg_project_512.json: for the three 512x512 projections (shadows) of the paper's
 constants PAPER_C[7], [0], [4] (max_iter 15, 256 march steps, 10 bisection steps, 16
