@@ -645,7 +645,10 @@ def main():
     outs = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
     # The work counter is a diagnostic output: timed launches leave it off (the kernel
     # variant without the per-sample add), one extra launch outside the timing fills it.
-    timed_outs = [{k: v for k, v in o.items() if k != "iters"} for o in outs]
+    # The timed launches write buffers of their own, compared bit for bit with the
+    # counting launch's after the timing.
+    timed_outs = [{k: v for k, v in dqj.alloc_outputs(p.width, p.height, extras=False).items()
+                   if k != "iters"} for p in ps]
 
     if args.kernel == "refill":
         count_plan = dqj.BatchPlan(ps, outs)
@@ -685,6 +688,11 @@ def main():
     ev_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
     hits = [int(o["mask"].sum().item()) for o in outs]
+    for f, (t, o) in enumerate(zip(timed_outs, outs)):
+        for k in ("mask", "depth", "shade"):
+            if not torch.equal(t[k], o[k]):
+                raise SystemExit(f"bench.py: timed output {k} of frame {f} differs from the "
+                                 "counting launch's")
 
     value = ialg / (ms_per_step * 1e-3)
     achieved_tf = FLOPS_PER_UPDATE * ialg / (ev_ms * 1e-3) / 1e12

@@ -98,6 +98,8 @@ def lib():
                                          C.POINTER(C.c_int64), C.c_int64, C.POINTER(C.c_uint8),
                                          C.POINTER(C.c_int32), C.c_int32]
         L.dqjo_classify_grid.restype = C.c_uint64
+        L.dqjo_shade_at.argtypes = [P, C.c_int32, C.c_int32, C.c_double, D, D]
+        L.dqjo_shade_at.restype = C.c_int32
         L.dqjo_params_size.restype = C.c_uint32
         _lib = L
     return _lib
@@ -243,6 +245,16 @@ def potential(p, x):
     sp = make_params(p)
     v = lib().dqjo_potential(C.byref(sp), _dptr(_vec(x, 3)), C.byref(m))
     return v, m.value
+
+
+def shade_at(p, i: int, j: int, t: float):
+    """(normal, shade) at depth t on pixel (i, j)'s ray, as a render's hit would get them."""
+    n = np.zeros(3)
+    sh = C.c_double(0.0)
+    sp = make_params(p)
+    if not lib().dqjo_shade_at(C.byref(sp), int(i), int(j), float(t), _dptr(n), C.byref(sh)):
+        raise ValueError("the ray misses the box")
+    return n, sh.value
 
 
 def render(p, pixels: Optional[Sequence[int]] = None, nthreads: int = 0) -> Dict[str, np.ndarray]:

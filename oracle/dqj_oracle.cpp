@@ -341,6 +341,39 @@ static double phong(const dqjo_params *p, const double n[3], const double d[3]) 
   return s;
 }
 
+// Section "Lighting/Illumination": the normal at a hit point ph is the normalised
+// central difference of the potential along the world axes (the ray's reversed
+// direction where the difference vanishes or is not finite); the shade is Eq. phong.
+// The 6 points' updates are added to *iters.
+static double hit_normal_shade(const dqjo_params *p, const double d[3], const double ph[3],
+                               double n[3], uint64_t *iters) {
+  // Central differences of the potential along the world axes.
+  double g[3];
+  for (int a = 0; a < 3; ++a) {
+    double xp[3] = {ph[0], ph[1], ph[2]};
+    double xm[3] = {ph[0], ph[1], ph[2]};
+    xp[a] = ph[a] + p->normal_h;
+    xm[a] = ph[a] - p->normal_h;
+    int32_t mp, mm;
+    const double gp = dqjo_potential(p, xp, &mp);
+    const double gm = dqjo_potential(p, xm, &mm);
+    *iters += (uint64_t)mp + (uint64_t)mm;
+    g[a] = gp - gm;
+  }
+  const double glen = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  if (glen > 0.0 && isfinite(glen)) {
+    n[0] = g[0] / glen;
+    n[1] = g[1] / glen;
+    n[2] = g[2] / glen;
+  } else {
+    n[0] = -d[0];
+    n[1] = -d[1];
+    n[2] = -d[2];
+  }
+
+  return phong(p, n, d);
+}
+
 static PixelResult render_pixel(const dqjo_params *p, int32_t i, int32_t j) {
   PixelResult res;
   res.mask = 0;
@@ -440,36 +473,21 @@ static PixelResult render_pixel(const dqjo_params *p, int32_t i, int32_t j) {
   // and the shade after every pixel has its depth; no update is spent on it here.
   if (p->normal_mode == 1) return res;
 
-  // Central differences of the potential along the world axes.
-  double g[3];
-  for (int a = 0; a < 3; ++a) {
-    double xp[3] = {ph[0], ph[1], ph[2]};
-    double xm[3] = {ph[0], ph[1], ph[2]};
-    xp[a] = ph[a] + p->normal_h;
-    xm[a] = ph[a] - p->normal_h;
-    int32_t mp, mm;
-    const double gp = dqjo_potential(p, xp, &mp);
-    const double gm = dqjo_potential(p, xm, &mm);
-    res.iters += (uint64_t)mp + (uint64_t)mm;
-    g[a] = gp - gm;
-  }
-  const double glen = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-  double n[3];
-  if (glen > 0.0 && isfinite(glen)) {
-    n[0] = g[0] / glen;
-    n[1] = g[1] / glen;
-    n[2] = g[2] / glen;
-  } else {
-    n[0] = -d[0];
-    n[1] = -d[1];
-    n[2] = -d[2];
-  }
-
-  res.shade = phong(p, n, d);
-  res.normal[0] = n[0];
-  res.normal[1] = n[1];
-  res.normal[2] = n[2];
+  res.shade = hit_normal_shade(p, d, ph, res.normal, &res.iters);
   return res;
+}
+
+// Normal and shade at a caller-given depth t on pixel (i, j)'s ray (the same steps as a
+// render's hit, at any point): for checking how a shade depends on where the hit lies.
+// Returns 0 when the ray misses the box (nothing written), 1 otherwise.
+int32_t dqjo_shade_at(const dqjo_params *p, int32_t i, int32_t j, double t, double normal[3],
+                      double *shade) {
+  double o[3], d[3], t0, t1;
+  if (!dqjo_ray(p, i, j, o, d, &t0, &t1)) return 0;
+  const double ph[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+  uint64_t iters = 0;
+  *shade = hit_normal_shade(p, d, ph, normal, &iters);
+  return 1;
 }
 
 // Paragraph "Lighting/Illumination": a normal from the surface through the hit points

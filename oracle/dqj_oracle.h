@@ -135,6 +135,11 @@ int32_t dqjo_scan_ray(const dqjo_params *p, int32_t i, int32_t j, double ta, dou
 
 uint32_t dqjo_params_size(void);
 
+/* Normal and shade (section "Lighting/Illumination", Eq. phong) at depth t on pixel
+ * (i, j)'s ray, by the same steps as a render's hit. Returns 0 if the ray misses the box. */
+int32_t dqjo_shade_at(const dqjo_params *p, int32_t i, int32_t j, double t, double normal[3],
+                      double *shade);
+
 #ifdef __cplusplus
 }
 #endif

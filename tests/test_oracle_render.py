@@ -192,3 +192,28 @@ def closed_inside(x, N):
         return True
     xr = math.log(4.0) / math.log(rad)
     return max(1, math.floor(math.log2(xr)) + 1) > N
+
+
+def test_shade_at_matches_render_and_c0_closed_form(oracle_mod):
+    """dqjo_shade_at repeats a render's normal and shade at any depth: at the render's
+    own depth it gives the render's values bit for bit, and on the c = 0 ball at the
+    analytic entry point the normal is radial."""
+    p = frame(W=24, H=24, N=12, S=64, B=8)
+    rho = 4.0 ** (2.0 ** -p.max_iter)
+    r = oracle_mod.render(p)
+    checked = 0
+    for j in range(p.height):
+        for i in range(p.width):
+            if not r["mask"][j, i]:
+                continue
+            n, sh = oracle_mod.shade_at(p, i, j, r["depth"][j, i])
+            assert sh == r["shade"][j, i] and np.array_equal(n, r["normal"][j, i])
+            _, o, d, _, _ = oracle_mod.ray(p, i, j)
+            ts, chord = analytic_ball(np.asarray(o), np.asarray(d), rho)
+            if ts is None or chord < 0.05:
+                continue
+            n2, _ = oracle_mod.shade_at(p, i, j, ts)
+            x = np.asarray(o) + ts * np.asarray(d)
+            assert math.acos(min(1.0, float(n2 @ (x / np.linalg.norm(x))))) < 1e-5
+            checked += 1
+    assert checked > 100
