@@ -129,6 +129,9 @@ extern "C" dqj_status dqj_autotune(const dqj_params *params, const dqj_frame_out
     const Cand cands[] = {{8, 8, 4, 8},   {8, 8, 4, 4},   {16, 8, 4, 8},  {16, 16, 4, 8},
                           {16, 16, 4, 4}, {32, 16, 4, 8}, {32, 32, 4, 8}, {8, 8, 2, 16},
                           {16, 16, 8, 4}, {64, 16, 4, 8}};
+    // timed without update counters: the kernel renders without one use
+    std::vector<dqj_frame_out> touts(outs, outs + n);
+    for (dqj_frame_out &o : touts) o.iters = nullptr;
     hipStream_t stream = nullptr;
     e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -147,7 +150,7 @@ extern "C" dqj_status dqj_autotune(const dqj_params *params, const dqj_frame_out
       sc.waves_per_block = c.wpb;
       sc.blocks_per_cu = c.bpc;
       dqj_batch_plan *plan = nullptr;
-      st = dqj_batch_plan_create(params, outs, n, &sc, stream, &plan);
+      st = dqj_batch_plan_create(params, touts.data(), n, &sc, stream, &plan);
       if (st != DQJ_OK) break;
       float ms = 1e30f;
       for (int rep = 0; rep < 3 && st == DQJ_OK; ++rep) {   // first replay warms up
