@@ -162,6 +162,23 @@ typedef struct dqj_frame_out {
  * validation and the launch; errors of the kernels surface as DQJ_E_DEVICE later. */
 dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dqj_render with the same arguments,
+ * outputs and results, except that it allocates nothing. dqj_render keeps its tile
+ * counter, and for split renders the hit and ambiguous ray lists, in device blocks it
+ * allocates per (device, stream) on first use; this entry point keeps them instead in
+ * one fixed device array of DQJ_NOALLOC_SCRATCH_BYTES per GPU, held from the library's
+ * first call on that GPU until the process ends. The array bounds the split frames it
+ * takes: precision SPLIT with width * height > DQJ_NOALLOC_MAX_SPLIT_PIXELS returns
+ * DQJ_E_INVALID before any launch. Every call on one GPU shares that GPU's array (each
+ * clears what it needs with a kernel of its own, never a memset), so calls that overlap
+ * on one GPU -- on two streams, or from two threads -- race and must be serialised by
+ * the caller; calls in one stream's order are safe. */
+#define DQJ_NOALLOC_MAX_SPLIT_PIXELS 524288u
+#define DQJ_NOALLOC_SCRATCH_BYTES (256u + 32u * DQJ_NOALLOC_MAX_SPLIT_PIXELS)
+dqj_status dqj_render_noalloc(const dqj_params *params, const dqj_frame_out *out,
+                              void *hip_stream);
+
 /* Render n frames (params[i] -> outs[i]) in one persistent launch over a global
  * (frame, tile) queue. All frames must share precision. */
 dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,

@@ -28,6 +28,7 @@ NORM_EUCLID8, NORM_REALPART = 0, 1
 PREC_FP32, PREC_SPLIT, PREC_FP64 = 0, 1, 2
 KERNEL_AUTO, KERNEL_REFILL, KERNEL_DIRECT, KERNEL_LOCKSTEP = 0, 1, 2, 3
 FLAG_BOX, FLAG_HIT, FLAG_FP64, FLAG_FALLBACK = 1, 2, 4, 8
+NOALLOC_MAX_SPLIT_PIXELS = 524288   # DQJ_NOALLOC_MAX_SPLIT_PIXELS
 
 
 class DQJError(RuntimeError):
@@ -168,6 +169,8 @@ _lib = None
 # symbol -> (restype, argtypes)
 _SIGS = {
     "dqj_render": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out), C.c_void_p]),
+    "dqj_render_noalloc": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out),
+                                       C.c_void_p]),
     "dqj_render_scheduled": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out),
                                          C.POINTER(dqj_schedule), C.c_void_p]),
     "dqj_render_batch": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out), C.c_int32,
@@ -366,6 +369,16 @@ def render(p, out: Optional[Dict] = None, stream=None, schedule: Optional[dqj_sc
     else:
         _check(lib().dqj_render_scheduled(C.byref(sp), C.byref(fo), C.byref(schedule),
                                           _stream(stream)))
+    return out
+
+
+def render_noalloc(p, out: Dict, stream=None) -> Dict:
+    """dqj_render_noalloc: one frame into the caller's outputs, with the library's fixed
+    per-GPU scratch instead of device memory allocated per stream. Split frames are
+    limited to NOALLOC_MAX_SPLIT_PIXELS; calls that overlap on one GPU race."""
+    sp = make_params(p)
+    fo = make_frame_out(out, p)
+    _check(lib().dqj_render_noalloc(C.byref(sp), C.byref(fo), _stream(stream)))
     return out
 
 

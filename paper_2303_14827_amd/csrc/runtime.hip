@@ -430,8 +430,48 @@ hipError_t stream_scratch(hipStream_t stream, size_t bytes, void **out) {
   return hipSuccess;
 }
 
-hipError_t launch_render_fp32(const KParams &P, const KOut &out, const Sched &s, int cus,
-                              hipStream_t stream) {
+// ---- fixed scratch of dqj_render_noalloc -------------------------------------
+// A file-scope device array, one copy per GPU, holds what dqj_render keeps in its
+// per-stream blocks: the tile counter and, for split renders, the hit and ambiguous
+// lists. On the host the array's name is only a stand-in: host code uses the address
+// hipGetSymbolAddress returns with the device current, looked up once per device.
+
+static_assert(split_scratch_bytes(DQJ_NOALLOC_MAX_SPLIT_PIXELS) == DQJ_NOALLOC_SCRATCH_BYTES,
+              "the fixed scratch holds the lists of the largest split frame it accepts");
+static __device__ __align__(256) unsigned char scratch[DQJ_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_fixed_mu;
+static void *g_fixed[kMaxDevices];
+
+static hipError_t fixed_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (!g_fixed[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_fixed[dev] = ptr;
+  }
+  *out = g_fixed[dev];
+  return hipSuccess;
+}
+
+// Tile counter of a persistent launch: the start of the fixed scratch when one is
+// given, else the stream's own block.
+static hipError_t launch_counter(void *fixed, hipStream_t stream, uint32_t **out) {
+  if (fixed) {
+    *out = (uint32_t *)fixed;
+    return hipSuccess;
+  }
+  return stream_counter(stream, out);
+}
+
+static hipError_t launch_render_fp32_at(const KParams &P, const KOut &out, const Sched &s, int cus,
+                                        void *fixed, hipStream_t stream) {
   if (s.kernel == DQJ_KERNEL_DIRECT) return launch_render_direct(P, out, stream);
   FrameDesc f;
   memset(&f, 0, sizeof f);
@@ -440,13 +480,20 @@ hipError_t launch_render_fp32(const KParams &P, const KOut &out, const Sched &s,
   f.tile_begin = 0;
   set_tiles(f, s.tile_w, s.tile_h);
   uint32_t *counter = nullptr;
-  hipError_t e = stream_counter(stream, &counter);
+  hipError_t e = launch_counter(fixed, stream, &counter);
   if (e != hipSuccess) return e;
   return launch_render_refill(f, counter, s, cus, stream);
 }
 
+hipError_t launch_render_fp32(const KParams &P, const KOut &out, const Sched &s, int cus,
+                              hipStream_t stream) {
+  return launch_render_fp32_at(P, out, s, cus, nullptr, stream);
+}
+
+// One frame. fixed: base of the fixed scratch (dqj_render_noalloc), or null to use
+// the stream's own blocks.
 static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out,
-                              const dqj_schedule *sched, hipStream_t stream) {
+                              const dqj_schedule *sched, hipStream_t stream, void *fixed = nullptr) {
   dqj_status s = validate_params(params);
   if (s != DQJ_OK) return s;
   s = check_render_modes(*params, true);
@@ -477,7 +524,7 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
       f.tile_begin = 0;
       set_tiles(f, sc.tile_w, sc.tile_h);
       uint32_t *counter = nullptr;
-      e = stream_counter(stream, &counter);
+      e = launch_counter(fixed, stream, &counter);
       if (e == hipSuccess) e = launch_render_de_lockstep(f, counter, sc, cus, stream);
     } else if (!sched || sched->kernel != DQJ_KERNEL_REFILL) {
       e = launch_render_de(kp, ko, (sched && sched->waves_per_block) ? sched->waves_per_block : 1,
@@ -490,7 +537,7 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
       f.tile_begin = 0;
       set_tiles(f, sc.tile_w, sc.tile_h);
       uint32_t *counter = nullptr;
-      e = stream_counter(stream, &counter);
+      e = launch_counter(fixed, stream, &counter);
       if (e == hipSuccess) e = launch_render_de_refill(f, counter, sc, cus, stream);
     }
     if (e == hipSuccess && kp.normal_mode != 0) e = launch_neighbour_normal(kp, ko, stream);
@@ -511,7 +558,7 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
   }
   switch (params->precision) {
     case DQJ_PREC_FP32:
-      e = launch_render_fp32(kp, ko, pick_schedule(sched, *params, cus), cus, stream);
+      e = launch_render_fp32_at(kp, ko, pick_schedule(sched, *params, cus), cus, fixed, stream);
       break;
     case DQJ_PREC_SPLIT: {
       const Sched s = pick_schedule(sched, *params, cus);
@@ -523,10 +570,19 @@ static dqj_status render_impl(const dqj_params *params, const dqj_frame_out *out
       f.tile_begin = 0;
       set_tiles(f, s.tile_w, s.tile_h);
       const uint64_t pixels = (uint64_t)params->width * (uint64_t)params->height;
-      void *scratch = nullptr;
-      e = stream_scratch(stream, split_scratch_bytes(pixels), &scratch);
-      if (e != hipSuccess) return fail(DQJ_E_NOMEM, "split scratch: %s", hipGetErrorString(e));
-      e = launch_render_split(f, split_scratch_at(scratch, pixels), s, cus, stream);
+      void *lists = fixed;
+      if (fixed) {
+        if (pixels > DQJ_NOALLOC_MAX_SPLIT_PIXELS)
+          return fail(DQJ_E_INVALID,
+                      "dqj_render_noalloc: a split frame of %llu pixels needs %zu bytes of scratch; "
+                      "the fixed scratch holds %u (at most %u pixels)",
+                      (unsigned long long)pixels, split_scratch_bytes(pixels),
+                      (unsigned)DQJ_NOALLOC_SCRATCH_BYTES, (unsigned)DQJ_NOALLOC_MAX_SPLIT_PIXELS);
+      } else {
+        e = stream_scratch(stream, split_scratch_bytes(pixels), &lists);
+        if (e != hipSuccess) return fail(DQJ_E_NOMEM, "split scratch: %s", hipGetErrorString(e));
+      }
+      e = launch_render_split(f, split_scratch_at(lists, pixels), s, cus, stream);
       break;
     }
     default:
@@ -555,6 +611,15 @@ extern "C" {
 
 dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *hip_stream) {
   DQJ_GUARD(return render_impl(params, out, nullptr, (hipStream_t)hip_stream);)
+}
+
+dqj_status dqj_render_noalloc(const dqj_params *params, const dqj_frame_out *out, void *hip_stream) {
+  DQJ_GUARD({
+    void *fixed = nullptr;
+    const hipError_t e = fixed_scratch(&fixed);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the fixed scratch");
+    return render_impl(params, out, nullptr, (hipStream_t)hip_stream, fixed);
+  })
 }
 
 dqj_status dqj_render_scheduled(const dqj_params *params, const dqj_frame_out *out,

@@ -24,7 +24,7 @@ struct SplitScratch {
   SplitEntry *amb;
 };
 
-inline size_t split_scratch_bytes(uint64_t pixels) {
+constexpr size_t split_scratch_bytes(uint64_t pixels) {
   return 256 + 2 * sizeof(SplitEntry) * (size_t)pixels;
 }
 
