@@ -27,9 +27,9 @@ METRIC = "Julia iters/sec & % FP32 VALU peak; p50/p99 frame latency served vs pl
 FLOPS_PER_UPDATE = 52
 FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak
 # Measured issue ceiling of v_fmac_f32 with vector-register operands on this GPU (no packed
-# FP32): 2.78 clocks per wave64 instruction at the nominal 2.4 GHz, i.e. 128 flops per
-# 1.158 ns per SIMD x 1024 SIMDs (profiles/gfx950_valu_issue.md).
-FP32_FMAC_ISSUE_TFLOPS = 113.2
+# FP32): 2.87 clocks per wave64 instruction at the nominal 2.4 GHz, i.e. 128 flops per
+# 1.196 ns per SIMD x 1024 SIMDs (profiles/gfx950_valu_issue.md).
+FP32_FMAC_ISSUE_TFLOPS = 109.6
 
 # HBM traffic of the timed plain_1024 kernel from two rocprofv3 --pmc runs (FETCH_SIZE and
 # WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB device copy;
