@@ -220,7 +220,7 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
         "plain": {"req_per_s": qn / qdur, "mpix_per_s": qp / qdur / 1e6,
                   "iters_per_s": qi / qdur, "makespan_s": qdur},
         "note": "iters = DQ updates counted on the GPU (split: FP16 march through the first "
-                "inside sample + FP32 window/bisection/normal + FP64 re-bisection; plain: "
+                "inside sample + FP32 re-check/bisection/normal + FP64 re-bisection; plain: "
                 "the method's count in FP32)"}
     return res
 

@@ -62,9 +62,13 @@ enum {
  * |a + b e| = |a| of the Introduction. */
 enum { DQJ_NORM_EUCLID8 = 0, DQJ_NORM_REALPART = 1 };
 
-/* Arithmetic of the render. FP32: every step in FP32. SPLIT: march in packed FP16,
- * bisection/normal/shade in FP32, rays whose FP32 in/out sequence around the FP16
- * crossing is ambiguous re-done in FP64. FP64: every step in FP64 on the GPU. */
+/* Arithmetic of the render. FP32: every step in FP32. SPLIT: march in packed FP16, which
+ * decides only escapes within its trust depth (N - ceil(N/4) updates, ceil(3N/8) for
+ * the real-part norm: FP16 orbits near the boundary part from exact ones after some
+ * updates); samples escaping later and
+ * the FP16 crossing are re-checked in FP32, which also bisects, takes the normal and
+ * shades; rays whose FP32 in/out test flips within fp64_window samples of the crossing
+ * are re-done in FP64. Same accuracy bar as FP32. FP64: every step in FP64 on the GPU. */
 enum { DQJ_PREC_FP32 = 0, DQJ_PREC_SPLIT = 1, DQJ_PREC_FP64 = 2 };
 
 typedef struct dqj_params {
@@ -165,7 +169,7 @@ dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): dqj_render with the same arguments,
  * outputs and results, except that it allocates nothing. dqj_render keeps its tile
- * counter, and for split renders the hit and ambiguous ray lists, in device blocks it
+ * counter, and for split renders the candidate and FP64 ray lists, in device blocks it
  * allocates per (device, stream) on first use; this entry point keeps them instead in
  * one fixed device array of DQJ_NOALLOC_SCRATCH_BYTES per GPU, held from the library's
  * first call on that GPU until the process ends. The array bounds the split frames it

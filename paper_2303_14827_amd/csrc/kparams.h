@@ -45,7 +45,9 @@ struct alignas(16) KParams {
   float ks;              // specular coefficient (0: none)
   float shininess;       // specular exponent
   float cull_r2;         // bounding sphere radius squared (0: none)
-  int32_t pad2[3];
+  int32_t T16;           // split precision: updates the FP16 march trusts (a sample
+                         // still bounded after T16 updates is a candidate crossing)
+  int32_t pad2[2];
 };
 static_assert(sizeof(KParams) % 16 == 0, "KParams must be 16-byte sized");
 

@@ -248,6 +248,16 @@ void pack_params(const dqj_params &p, KParams &k) {
   k.B = p.bisect_steps;
   k.norm = p.norm;
   k.fp64_window = p.fp64_window;
+  // FP16 orbits of points near the set's boundary part from the exact orbit after some
+  // updates, so the FP16 march trusts an escape only when it comes within T16 updates;
+  // samples that escape later are re-checked in FP32. T16 = N - ceil(N/4) with the
+  // 8-square norm, ceil(3N/8) with the real-part norm, whose set is rougher (measured on
+  // FP16-emulated orbits against FP64: these depths lose no crossing on sampled rays).
+  {
+    const int N = p.max_iter;
+    const int t = p.norm == DQJ_NORM_REALPART ? (3 * N + 7) / 8 : N - (N + 3) / 4;
+    k.T16 = t > 1 ? t : 1;
+  }
   k.march = p.march;
   k.de_eps = (float)p.de_hit_eps;
   k.de_min_step = (float)p.de_min_step;
@@ -432,7 +442,7 @@ hipError_t stream_scratch(hipStream_t stream, size_t bytes, void **out) {
 
 // ---- fixed scratch of dqj_render_noalloc -------------------------------------
 // A file-scope device array, one copy per GPU, holds what dqj_render keeps in its
-// per-stream blocks: the tile counter and, for split renders, the hit and ambiguous
+// per-stream blocks: the tile counter and, for split renders, the candidate and FP64
 // lists. On the host the array's name is only a stand-in: host code uses the address
 // hipGetSymbolAddress returns with the device current, looked up once per device.
 

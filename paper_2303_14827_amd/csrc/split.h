@@ -7,13 +7,15 @@
 
 namespace dqj {
 
-// A ray the FP16 march found inside at sample khat (hit list), or one whose FP32
-// window check was ambiguous (FP64 list).
+// A ray of the candidate list: the FP32 pass scans it from sample khat - w; kend < 0:
+// the FP16 march found an inside sample, and the scan runs to the first FP32 inside
+// sample; kend >= 0: no FP16 inside sample, and the scan ends after sample kend + w.
+// On the FP64 list, khat is the sample the FP64 pass starts from (less w).
 struct SplitEntry {
   uint32_t frame;
   uint32_t pix;
   int32_t khat;
-  uint32_t pad;
+  int32_t kend;
 };
 
 // Device scratch of one split launch: ctr[0] tile counter, ctr[1] hit-list length,

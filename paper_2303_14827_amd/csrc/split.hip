@@ -4,25 +4,28 @@
 //      owns a ray and classifies two consecutive samples k, k+1 per packed register
 //      (half2), so every v_pk_fma_f16 advances two samples. Escape is tracked as the
 //      running maximum of ||z_n||^2 (v_pk_max_f16 ignores NaN, so an escaped half stays
-//      escaped after it overflows), which is exactly "||z_n||^2 > R^2 for some n <= N".
-//      The first inside FP16 sample k^ of each ray goes to a compacted hit list; rays
-//      with no inside sample are written as misses.
-//   2. refine_fp32: for each listed ray, classify the window k^-w .. k^+w in FP32. If the
-//      FP32 classes there are monotone (out ... out in ... in) with the change inside the
-//      window, the first FP32 inside sample k is the crossing: bisect [t_{k-1}, t_k] in
-//      FP32, take the central-difference normal and shade. Otherwise (the classes flip
-//      more than once, or all agree so the change lies outside the window) the ray is
-//      ambiguous and goes to a second list.
-//   3. rebisect_fp64: for each ambiguous ray, classify the window in FP64, take its first
-//      inside sample (marching on past the window in FP64 if there is none, and back to the
-//      start of the inside run if the window's first sample is already inside), then
-//      bisect, take the normal and shade in FP64.
+//      escaped after it overflows). FP16 orbits near the set's boundary part from the
+//      exact ones after some updates, so the march trusts an escape only when it came
+//      within T16 = N - ceil(N/4) updates: the samples of pairs that escaped later span a
+//      range [kcf, kcl] that FP32 re-checks. The first pair still bounded after N updates
+//      gives the FP16 inside sample khat. A ray with neither is a miss; every other ray
+//      goes to a compacted candidate list.
+//   2. verify_fp32: for each listed ray, classify in FP32 from min(kcf, khat) - w to the
+//      first inside sample k32 (up to kcl + w when there is no khat: past it, a miss),
+//      confirm that samples k32+1 .. k32+w are inside too, bisect [t_{k32-1}, t_{k32}] in
+//      FP32, take the central-difference normal and shade. A ray whose FP32 classes flip
+//      within the window after k32, or whose scan starts inside, goes to a second list.
+//   3. rebisect_fp64: for each ray of the second list, classify from k - w in FP64 (k
+//      the listed sample) to the first inside sample, marching on past the window if
+//      needed and back to the start of the inside run if the first sample is already
+//      inside, then bisect, take the normal and shade in FP64.
 // The three kernels run back to back on one stream; list lengths stay on the device.
 #include <cstring>
 
 #include "dq_device.h"
 #include "launch.h"
 #include "persist.h"
+#include "qform.h"
 #include "refill.h"
 #include "split.h"
 
@@ -273,6 +276,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
   float Sf = 0.0f, Sf2h = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
   int N = 1;
   bool n_is_1 = false;
+  int TmN = 0;   // T16 - N: a pair that escaped after at least T16 updates came near the set
   // Trip counter and deadlines as in the FP32 marcher (wrap-safe compare; idle lanes
   // hold a NaN state, which the running maximum ignores, and a deadline 2^31 - 1 ahead).
   uint32_t trip = 0;
@@ -288,6 +292,9 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
   // Sample k of the ray is eye + (t0 + k dt) d, computed as k D + X0 with D = dt d and
   // X0 = eye + t0 d (FP32, then rounded to FP16).
   float X0 = 0, Y0 = 0, Z0 = 0, DX = 0, DY = 0, DZ = 0, kp = 0.0f;   // kp: low sample of the pair
+  // First and last sample of pairs that escaped only after T16 or more updates (-1: none):
+  // the FP32 pass re-checks that range.
+  float kcf = -1.0f, kcl = -1.0f;
   uint32_t cnt_lo = 0, cnt_hi = 0, it_lane = 0;
 
   for (;;) {
@@ -313,13 +320,31 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
     const uint64_t due_m = __builtin_amdgcn_ballot_w64((int)(trip - dl) >= 0);
     if (__builtin_amdgcn_inverse_ballot_w64((both_m & last_m) | (due_m & ~both_m))) {
       const bool esc_lo = m2.x > R2;
-      if (both) {
+      // a last pair that escaped late still extends the range to re-check
+      if (both && (int)(trip - dl) >= TmN) {
+        kcf = kcf < 0.0f ? kp : kcf;
+        kcl = kp + 1.0f;
+      }
+      if (both && kcf < 0.0f) {   // every sample escaped within T16 updates: a miss
         if (COUNT) it_lane += cnt_lo + cnt_hi;
         write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
       } else {
-        if (COUNT) it_lane += cnt_lo + (esc_lo ? cnt_hi : 0u);
+        // an FP16 inside sample khat (the pair reached max_iter): the FP32 pass scans from
+        // the first late-escaping sample, or from khat, to its own first inside sample;
+        // a ray without one: the FP32 pass re-checks [kcf, kcl]
+        int32_t kc, kend;
+        if (both) {
+          if (COUNT) it_lane += cnt_lo + cnt_hi;
+          kc = (int32_t)kcf;
+          kend = (int32_t)kcl;
+        } else {
+          if (COUNT) it_lane += cnt_lo + (esc_lo ? cnt_hi : 0u);
+          const int32_t khat = (int32_t)kp + (esc_lo ? 1 : 0);
+          kc = kcf >= 0.0f && (int32_t)kcf < khat ? (int32_t)kcf : khat;
+          kend = -1;
+        }
         const uint32_t slot = atomicAdd(ctr + 1, 1u);
-        hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, (int32_t)kp + (esc_lo ? 1 : 0), 0u};
+        hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, kc, kend};
       }
       busy = 0;
       z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = kNaN2;
@@ -330,6 +355,10 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
     // (the pair's test from before the slow path: the lanes it ended fail it too)
     if (__builtin_amdgcn_inverse_ballot_w64(both_m & ~last_m)) {
       if (COUNT) it_lane += cnt_lo + cnt_hi;
+      if ((int)(trip - dl) >= TmN) {   // the pair took T16 or more updates to escape
+        kcf = kcf < 0.0f ? kp : kcf;
+        kcl = kp + 1.0f;
+      }
       kp += 2.0f;
       // The high half of the last pair lies past sample S when S is even. Without
       // counting it is pointed at sample S again (a duplicate cannot change the pair's
@@ -415,6 +444,7 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           }
           R2 = (_Float16)uniform_f(F->P.R2);
           N = (int)uniform((uint32_t)F->P.N);
+          TmN = (int)uniform((uint32_t)(F->P.T16 - F->P.N));
           ex = uniform_f(F->P.eye[0]);
           ey = uniform_f(F->P.eye[1]);
           ez = uniform_f(F->P.eye[2]);
@@ -456,6 +486,8 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
             z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = hsplat(0.0f);
             s = hsplat(0.0f);
             dl = trip + (uint32_t)N;
+            kcf = -1.0f;
+            kcl = -1.0f;
             if (COUNT) cnt_lo = cnt_hi = 0;
           } else {
             write_pixel(F->out, pix, miss_pixel(0));
@@ -473,19 +505,24 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
 }
 
 // ---------------------------------------------------------------------------
-// 2. FP32 verify window + bisection + normal + shade over the hit list
+// 2. FP32 pass over the candidate list
 // ---------------------------------------------------------------------------
+// One lane per listed ray: FP32 samples k = max(khat - w, 0), ... up to the first inside
+// one, k32 (to the last sample when the FP16 march found an inside sample, else to
+// kend + w: past that range every sample escaped within T16 FP16 updates). If the scan
+// starts inside (k32 = khat - w > 0), the crossing lies before it; if a sample of
+// k32 + 1 .. k32 + w is outside, the FP32 classes flip within the window. Both go to
+// the FP64 list. Otherwise bisect [t(k32 - 1), t(k32)] in FP32, take the normal and shade.
+// Waves take 64 consecutive entries per step, so their lanes meet at the end of every
+// step for the work-counter reduction.
 template <int NORM, bool BATCH, bool COUNT>
-__global__ __launch_bounds__(256) void refine_fp32_kernel(FrameDesc single,
+__global__ __launch_bounds__(256) void verify_fp32_kernel(FrameDesc single,
                                                           const FrameDesc *__restrict__ table,
-                                                          const uint32_t *__restrict__ ctr,
+                                                          uint32_t *__restrict__ ctr,
                                                           const SplitEntry *__restrict__ hits,
-                                                          uint32_t *__restrict__ amb_ctr,
                                                           SplitEntry *__restrict__ amb) {
   const ConstFrame ctable = (ConstFrame)table;
   const uint32_t n = ctr[1];
-  // wave-uniform loop: each wave takes 64 consecutive entries per step, so its lanes
-  // meet again at the end of every step for the work-counter reduction
   const uint32_t wave0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t base = wave0; base < n; base += stride) {
@@ -505,36 +542,40 @@ __global__ __launch_bounds__(256) void refine_fp32_kernel(FrameDesc single,
       const int i = (int)(en.pix % (uint32_t)P.W), j = (int)(en.pix / (uint32_t)P.W);
       float d[3], t0, t1;
       pixel_dir(P, i, j, d);
-      clip_box(P, d, t0, t1);
+      clip_box(P, d, t0, t1);   // the FP16 march found this ray's segment with the same code
       const float dt = (t1 - t0) / (float)P.S;
-      const int w = P.fp64_window;
-      const int kh = en.khat;
-      const int klo = kh - w > 0 ? kh - w : 0;
-      const int khi = kh + w < P.S ? kh + w : P.S;
-      uint32_t in_mask = 0;
-      for (int k = klo; k <= khi; ++k) {
+      const int w = P.fp64_window, S = P.S;
+      const int ks = en.khat - w > 0 ? en.khat - w : 0;
+      const int klast = en.kend < 0 ? S : (en.kend + w < S ? en.kend + w : S);
+      int k32 = -1;
+      for (int k = ks; k <= klast; ++k) {
         bool in;
         float n2;
         it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)k, dt, t0), d, 0.0f, 0.0f, 0.0f, &in,
                                &n2);
-        in_mask |= (in ? 1u : 0u) << (k - klo);
+        if (in) {
+          k32 = k;
+          break;
+        }
       }
-      // The FP32 window decides the crossing when its classes are monotone
-      // (out ... out in ... in) with the change inside the window: an outside sample
-      // before the first inside one, or the first inside one is sample 0.
-      const uint32_t full = (2u << (khi - klo)) - 1u;
-      const uint32_t low = in_mask & (0u - in_mask);
-      const bool monotone = in_mask != 0 && ((in_mask | (low - 1u)) == full);
-      const int kfirst = klo + (in_mask ? __builtin_ctz(in_mask) : 0);
-      const bool decided = monotone && (kfirst > klo || kfirst == 0);
-      if (decided) {
+      bool to_fp64 = k32 == ks && ks > 0;
+      for (int jj = 1; k32 >= 0 && !to_fp64 && jj <= w && k32 + jj <= S; ++jj) {
+        bool in;
+        float n2;
+        it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)(k32 + jj), dt, t0), d, 0.0f, 0.0f,
+                               0.0f, &in, &n2);
+        to_fp64 = !in;
+      }
+      if (to_fp64) {
+        const uint32_t slot = atomicAdd(ctr + 2, 1u);
+        amb[slot] = SplitEntry{en.frame, en.pix, (int32_t)k32, -1};
+      } else if (k32 < 0) {
+        write_pixel(F->out, en.pix, miss_pixel(DQJ_FLAG_BOX));
+      } else {
         PixelOut r;
-        it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, kfirst,
+        it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, k32,
                                (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
         write_pixel(F->out, en.pix, r);
-      } else {
-        const uint32_t slot = atomicAdd(amb_ctr, 1u);
-        amb[slot] = en;
       }
     }
     if (COUNT) wave_add_by_frame(fr, it, F);
@@ -542,7 +583,7 @@ __global__ __launch_bounds__(256) void refine_fp32_kernel(FrameDesc single,
 }
 
 // ---------------------------------------------------------------------------
-// 3. FP64 re-march of the window and re-bisection over the ambiguous list
+// 3. FP64 march and re-bisection over the rays the FP32 pass hands on
 // ---------------------------------------------------------------------------
 template <int NORM, bool BATCH, bool COUNT>
 __global__ __launch_bounds__(256) void rebisect_fp64_kernel(FrameDesc single,
@@ -639,18 +680,18 @@ static void launch_split_variant(const FrameDesc &single, const FrameDesc *table
       DQJ_MARCH(1, false);
   }
 #undef DQJ_MARCH
-  const int rblocks = cus * 8;
+  const int vblocks = cus * 8;
+#define DQJ_VERIFY(NM)                                                                            \
+  hipLaunchKernelGGL((verify_fp32_kernel<NM, BATCH, COUNT>), dim3(vblocks), dim3(256), 0,          \
+                     stream, single, table, sc.ctr, sc.hits, sc.amb);                               \
+  hipLaunchKernelGGL((rebisect_fp64_kernel<NM, BATCH, COUNT>), dim3(cus * 2), dim3(256), 0, stream, \
+                     single, table, sc.ctr + 2, sc.amb)
   if (norm == 0) {
-    hipLaunchKernelGGL((refine_fp32_kernel<0, BATCH, COUNT>), dim3(rblocks), dim3(256), 0, stream,
-                       single, table, sc.ctr, sc.hits, sc.ctr + 2, sc.amb);
-    hipLaunchKernelGGL((rebisect_fp64_kernel<0, BATCH, COUNT>), dim3(cus * 2), dim3(256), 0,
-                       stream, single, table, sc.ctr + 2, sc.amb);
+    DQJ_VERIFY(0);
   } else {
-    hipLaunchKernelGGL((refine_fp32_kernel<1, BATCH, COUNT>), dim3(rblocks), dim3(256), 0, stream,
-                       single, table, sc.ctr, sc.hits, sc.ctr + 2, sc.amb);
-    hipLaunchKernelGGL((rebisect_fp64_kernel<1, BATCH, COUNT>), dim3(cus * 2), dim3(256), 0,
-                       stream, single, table, sc.ctr + 2, sc.amb);
+    DQJ_VERIFY(1);
   }
+#undef DQJ_VERIFY
 }
 
 template <bool BATCH>

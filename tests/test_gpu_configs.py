@@ -20,8 +20,8 @@ from parity import assert_parity, compare, sample_pixels, to_numpy
 
 pytestmark = pytest.mark.gpu
 
-SPLIT_MIN_AGREE = 0.995
-SPLIT_SHADE_FRAC = 0.995
+SPLIT_MIN_AGREE = 0.999
+SPLIT_SHADE_FRAC = 0.999
 
 
 def say(*a):

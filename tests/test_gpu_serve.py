@@ -88,7 +88,7 @@ def test_served_split_against_oracle(dqj):
         ora = oracle.render(p, pixels=pix)
         rep = compare(p, g, ora, pixels=pix)
         say(p.width, p.max_iter, {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
-        assert_parity(rep, 0.995, 0.995)
+        assert_parity(rep, 0.999, 0.999)
 
 
 def test_refusals_cancel_timeout(dqj):

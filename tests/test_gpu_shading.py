@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 KERNELS = ["refill", "direct", "de", "split"]
 BARS = {"refill": (0.999, 0.999), "direct": (0.999, 0.999), "de": (0.999, 0.99),
-        "split": (0.995, 0.995)}
+        "split": (0.999, 0.999)}
 
 
 def say(*a):

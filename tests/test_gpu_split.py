@@ -1,13 +1,8 @@
-"""GPU split-precision path (packed FP16 march, FP32 verify + bisection, FP64
-re-bisection of ambiguous rays) against the FP64 oracle.
-
-The split path's error per frame is reported like the FP32 path's (mask
-agreement, depth error in units of the box diagonal, shade error). Its stated bar
-is looser than the FP32 path's: rays the FP16 march misses entirely, and crossings
-before the FP32 window, are not re-checked, so >= 99.5 % of pixels must agree and
->= 99.5 % of agreeing hits must shade within 1/255; every mismatch must still sit
-within one march step of the set's boundary, and depth on agreeing hits within
-1e-4 of the box diagonal.
+"""GPU split-precision path (packed FP16 march to a candidate crossing, FP32
+continuation + bisection, FP64 re-bisection of rays whose FP32 classes flip) against
+the FP64 oracle, at the FP32 path's bar: >= 99.9 % of pixels agree, every mismatch
+within one march step of the set's boundary, depth on agreeing hits within 1e-4 of
+the box diagonal, shade within 1/255 on >= 99.9 % of agreeing hits.
 """
 import sys
 
@@ -17,8 +12,8 @@ import pytest
 import workloads
 from parity import assert_parity, compare, to_numpy
 
-SPLIT_MIN_AGREE = 0.995
-SPLIT_SHADE_FRAC = 0.995
+SPLIT_MIN_AGREE = 0.999
+SPLIT_SHADE_FRAC = 0.999
 
 pytestmark = pytest.mark.gpu
 
@@ -93,13 +88,7 @@ def test_split_edge_cases(dqj, oracle_mod):
         o = oracle_mod.render(p)
         rep = compare(p, g, o)
         say(" ", {k: v for k, v in rep.items() if k != "mismatch_far_from_boundary"})
-        if p.norm == workloads.NORM_REALPART:
-            # This constant's real-part set is so rough that most +-2 windows around the
-            # crossing flip more than once and FP16 misplaces the first inside sample by
-            # more than the window on ~8 % of hit rays: stated bar 99 % for this case.
-            assert_parity(rep, 0.99, 0.99)
-        else:
-            assert_parity(rep, SPLIT_MIN_AGREE, SPLIT_SHADE_FRAC)
+        assert_parity(rep, SPLIT_MIN_AGREE, SPLIT_SHADE_FRAC)
 
 
 def test_split_batch_matches_single(dqj):
