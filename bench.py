@@ -112,23 +112,46 @@ def _pct(xs, q):
     return float(np.quantile(np.asarray(xs), q)) if len(xs) else None
 
 
-def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
+def _tail(recs, keys, q=0.99):
+    """p50/p99 of the latency and, for the requests at or above the p99 latency, the mean
+    of each latency component (ms) and their sizes."""
+    import numpy as np
+    lat = np.asarray([r["lat"] for r in recs])
+    thr = float(np.quantile(lat, q))
+    tail = [r for r in recs if r["lat"] >= thr]
+    out = {"p50_ms": 1e3 * float(np.quantile(lat, 0.5)), "p99_ms": 1e3 * thr,
+           "max_ms": 1e3 * float(lat.max()), "tail_requests": len(tail)}
+    out["tail_mean_ms"] = {k: 1e3 * float(np.mean([r[k] for r in tail])) for k in ("lat",) + keys}
+    sides = {}
+    for r in tail:
+        sides[r["side"]] = sides.get(r["side"], 0) + 1
+    out["tail_sides"] = {str(k): v for k, v in sorted(sides.items())}
+    out["tail_max_iter_mean"] = float(np.mean([r["max_iter"] for r in tail]))
+    return out
+
+
+def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=None, slots=0):
     """The request stream replayed against the server (continuous batching; split
     precision, the stream's own, and FP32) and against the plain path (one FP32 dqj_render
     at a time, FIFO).
 
     Open loop: requests are submitted at their scheduled (Poisson) arrival times;
-    latency = completion seen by the host - scheduled arrival. Closed loop
-    ("capacity"): the first capacity_n requests submitted back to back; throughput =
-    requests, pixels and GPU-counted DQ updates over the makespan.
+    latency = completion seen by the host - scheduled arrival. Served latency splits into
+    admit wait (arrival to admission), first-launch wait (admission to the first epoch
+    holding one of its tiles) and run (first launch to completion); plain latency into
+    queue wait (arrival to the start of its render) and render. The p99 tail is reported
+    with the mean of each component. Closed loop ("capacity"): the first capacity_n
+    requests submitted back to back; throughput = requests, pixels and GPU-counted DQ
+    updates over the makespan.
     """
     import threading
     import queue as q
 
     stream = workloads.serve_stream(duration_s=duration_s, rate_hz=rate_hz)
+    policy = dqj.SERVE_FAIR if policy is None else policy
 
     def served(arrivals, open_loop, precision=workloads.PREC_SPLIT):
-        srv = dqj.Server(precision=precision, count_iters=True)
+        srv = dqj.Server(precision=precision, count_iters=True, policy=policy, slots=slots)
         pend = q.Queue()
         t0 = time.monotonic() + 0.05
 
@@ -149,7 +172,7 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
         th = threading.Thread(target=submitter)
         start = time.monotonic()
         th.start()
-        lats, counters, pixels, n = [], [], 0, 0
+        recs, counters, pixels, n = [], [], 0, 0
         while True:
             item = pend.get()
             if item is None:
@@ -157,7 +180,10 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
             tk, t_arr, out, p = item
             r = srv.wait(tk)
             assert r["status"] == dqj.OK, r
-            lats.append(r["t_done"] - t_arr)
+            recs.append({"lat": r["t_done"] - t_arr, "admit_wait": r["t_admit"] - t_arr,
+                         "first_launch_wait": r["t_first_launch"] - r["t_admit"],
+                         "run": r["t_done"] - r["t_first_launch"], "side": p.width,
+                         "max_iter": p.max_iter})
             counters.append(out["iters"])   # summed once at the end, off the critical path
             pixels += p.pixels
             n += 1
@@ -166,12 +192,12 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
         iters = int(torch.stack(counters).sum().item())
         st = srv.stats()
         srv.close()
-        return lats, iters, pixels, n, end - start, st
+        return recs, iters, pixels, n, end - start, st
 
     def plain(arrivals, open_loop):
         s = torch.cuda.current_stream()
         t0 = time.monotonic() + 0.05
-        lats, counters, pixels = [], [], 0
+        recs, counters, pixels = [], [], 0
         start = time.monotonic()
         for a in arrivals:
             p = a.params.replace(precision=workloads.PREC_FP32)
@@ -183,30 +209,33 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch):
             else:
                 t_arr = time.monotonic()
             out = dqj.alloc_outputs(p.width, p.height, extras=False)
+            t_start = time.monotonic()
             dqj.render(p, out=out, stream=s)
             s.synchronize()
-            lats.append(time.monotonic() - t_arr)
+            t_end = time.monotonic()
+            recs.append({"lat": t_end - t_arr, "queue_wait": t_start - t_arr, "render": t_end - t_start,
+                         "side": p.width, "max_iter": p.max_iter})
             counters.append(out["iters"])
             pixels += p.pixels
         dur = time.monotonic() - start
-        return lats, int(torch.stack(counters).sum().item()), pixels, len(arrivals), dur
+        return recs, int(torch.stack(counters).sum().item()), pixels, len(arrivals), dur
 
+    served_keys = ("admit_wait", "first_launch_wait", "run")
     res = {"stream": f"Poisson {rate_hz:g} req/s for {duration_s:g} s ({len(stream)} requests), "
                      "side uniform over {128,256,512,1024,2048}, max_iter U[8,64], "
                      "march steps 16*max_iter, 10 bisection steps",
-           "requests": len(stream)}
-    sl, si, sp, sn, sdur, sst = served(stream, True)
-    res["served"] = {"precision": "split (FP16 march, FP32 bisection, FP64 re-bisection)",
-                     "p50_ms": 1e3 * _pct(sl, 0.5), "p99_ms": 1e3 * _pct(sl, 0.99),
-                     "max_ms": 1e3 * max(sl), "epochs": sst["epochs"]}
-    fl, fi, fp, fn, fdur, fst = served(stream, True, workloads.PREC_FP32)
+           "requests": len(stream),
+           "policy": "oldest first" if policy == dqj.SERVE_OLDEST else "fair share",
+           "slots": slots or 3}
+    sr, si, sp, sn, sdur, sst = served(stream, True)
+    res["served"] = {"precision": "split (FP16 march, FP32 re-check and bisection, FP64 re-bisection)",
+                     **_tail(sr, served_keys), "epochs": sst["epochs"]}
+    fr, fi, fp, fn, fdur, fst = served(stream, True, workloads.PREC_FP32)
     res["served_fp32"] = {"precision": "FP32 (the plain path's kernels, continuously batched)",
-                          "p50_ms": 1e3 * _pct(fl, 0.5), "p99_ms": 1e3 * _pct(fl, 0.99),
-                          "max_ms": 1e3 * max(fl), "epochs": fst["epochs"]}
-    pl, pi, pp, pn, pdur = plain(stream, True)
+                          **_tail(fr, served_keys), "epochs": fst["epochs"]}
+    pr, pi, pp, pn, pdur = plain(stream, True)
     res["plain"] = {"precision": "FP32, one request at a time, FIFO",
-                    "p50_ms": 1e3 * _pct(pl, 0.5), "p99_ms": 1e3 * _pct(pl, 0.99),
-                    "max_ms": 1e3 * max(pl)}
+                    **_tail(pr, ("queue_wait", "render"))}
     cap = stream[:capacity_n]
     cl, ci, cp, cn, cdur, _ = served(cap, False)
     gl, gi, gp, gn, gdur, _ = served(cap, False, workloads.PREC_FP32)
@@ -591,8 +620,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel", choices=["refill", "direct"], default="refill")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the served request stream (0: skip; the full stream is 60)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the served request stream (0: skip)")
+    ap.add_argument("--serve-policy", choices=["fair", "oldest"], default="fair")
+    ap.add_argument("--serve-slots", type=int, default=0, help="epoch slots (0: the library default)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--capacity-requests", type=int, default=300)
     ap.add_argument("--workload", choices=["plain_1024", "split_1080p", "sweep_256", "de_1024",
@@ -733,7 +764,9 @@ def main():
     }
     if args.serve_seconds > 0:
         line["serve"] = serve_bench(args.serve_seconds, args.serve_rate, args.capacity_requests,
-                                    dqj, workloads, torch)
+                                    dqj, workloads, torch,
+                                    dqj.SERVE_OLDEST if args.serve_policy == "oldest" else dqj.SERVE_FAIR,
+                                    args.serve_slots)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
     if args.kernel == "refill":
