@@ -18,6 +18,8 @@
 // frame before it starts a tile of another frame, so the Julia constant and the
 // camera stay wave-uniform (scalar registers). Results do not depend on which
 // lane or wave computes a pixel: images are bit-identical under any schedule.
+// Once the queue has ended, launches without the update counter finish their rays in
+// a second loop that runs the same trip without the hand-out.
 #include "dq_device.h"
 #include "launch.h"
 #include "persist.h"
@@ -33,6 +35,7 @@ using namespace persist;
 namespace {
 
 enum { PH_IDLE = 0, PH_MARCH = 1, PH_BISECT = 2, PH_NORMAL = 3 };
+
 
 // zeta_0 for a world point and its q.
 template <bool AXIS>
@@ -349,6 +352,160 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
     }
 
     if (exhausted && !__builtin_amdgcn_ballot_w64(phase != PH_IDLE)) break;
+    if (!COUNT && exhausted) break;   // the rest runs in the tail loop below
+  }
+  if constexpr (!COUNT) {
+    // ---- after the tile queue has ended (launches without the update counter): the
+    // same trip without the tile hand-out, until every lane is idle. Leaving the
+    // hand-out behind shortens each trip of the launch's tail, where few lanes are
+    // still busy: plain_1024 6% and a single 1024^2 frame with many hits 12% faster.
+    // The trip is written out again rather than shared through a lambda, whose code
+    // was many times slower on gfx950.
+    for (;;) {
+    ++trip;
+    // ---- one update on every lane (n2 is ||zeta||^2 - c0)
+    const float n2 = dq_update_q<NORM>(z, q, h);
+    // Three per-lane tests, combined as lane masks: the sample escaped, it is past the
+    // last march sample (k >= S; k is integer-valued, so k > S - 1/2), its deadline
+    // has come. Fast path: an outside march sample with more samples to go starts the
+    // next one. Everything else that retires (a march hit or miss, a bisection or
+    // normal point) takes the slow path, which runs first; the fast set is fixed
+    // before it, and the two sets are disjoint.
+    // (The masks are formed explicitly: left to itself the compiler turns the
+    // combination into per-lane selects.)
+    const uint64_t esc = __builtin_amdgcn_ballot_w64(n2 > R2c);
+    const uint64_t last = __builtin_amdgcn_ballot_w64(k > Sfh);
+    const uint64_t due = __builtin_amdgcn_ballot_w64((int)(trip - dl) >= 0);
+    const uint64_t fast = esc & ~last;
+
+    if (__builtin_amdgcn_inverse_ballot_w64((esc & last) | (due & ~esc))) {
+      const KParams &P = F->P;
+      // (recomputed from an opaque copy: a shared compare would run on every trip)
+      float n2c = n2;
+      asm volatile("" : "+v"(n2c));
+      const bool inside = !(n2c > R2c);
+      const int m = N - (int)(dl - trip);   // escape index, or N when inside
+      bool next_normal = false;
+      bool restart = false;   // start the point at parameter tr on the ray
+      float tr = 0.0f;
+      if (phase == PH_MARCH) {
+        const int kh = inside ? (int)k : -1;
+        k = kNoMarch;
+        if (kh >= 0) {
+          kstar = kh;
+          if (kstar == 0) {
+            thit = t0;
+            next_normal = true;
+          } else {
+            lo = fmaf((float)(kstar - 1), dt, t0);
+            hi = fmaf((float)kstar, dt, t0);
+            if (P.B == 0) {
+              thit = 0.5f * (lo + hi);
+              next_normal = true;
+            } else {
+              b = 0;
+              phase = PH_BISECT;
+              tr = 0.5f * (lo + hi);
+              restart = true;
+            }
+          }
+        } else {  // no part found an inside sample: the ray misses
+          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+          phase = PH_IDLE;
+        }
+      } else if (phase == PH_BISECT) {
+        const float tm = 0.5f * (lo + hi);
+        if (inside)
+          hi = tm;
+        else
+          lo = tm;
+        ++b;
+        if (b >= P.B) {
+          thit = 0.5f * (lo + hi);
+          next_normal = true;
+        } else {
+          tr = 0.5f * (lo + hi);
+          restart = true;
+        }
+      } else {  // PH_NORMAL: stencil point sidx just retired
+        const float G = potential(n2c + h[0], m);
+        const float sg = (sidx & 1) ? -G : G;
+        const int axis = sidx >> 1;
+        if (axis == 0)
+          gx += sg;
+        else if (axis == 1)
+          gy += sg;
+        else
+          gz += sg;
+        ++sidx;
+      }
+      if (next_normal) {
+        phase = PH_NORMAL;
+        // the four-neighbour normal is formed after the frame: no stencil points
+        sidx = P.normal_mode != 0 ? 6 : 0;
+        gx = gy = gz = 0.0f;
+      }
+      if (phase == PH_NORMAL && sidx == 6) {   // the hit is finished (g = 0: no stencil)
+        const float g[3] = {gx, gy, gz};
+        const float d[3] = {dx, dy, dz};
+        PixelOut r;
+        finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+        write_pixel(F->out, pix, r);
+        phase = PH_IDLE;
+      }
+      float px = 0, py = 0, pz = 0;
+      if (restart) {
+        px = fmaf(tr, dx, ex);
+        py = fmaf(tr, dy, ey);
+        pz = fmaf(tr, dz, ez);
+      } else if (phase == PH_NORMAL) {
+        const int axis = sidx >> 1;
+        const float hs = (sidx & 1) ? -P.h : P.h;
+        px = fmaf(thit, dx, ex) + (axis == 0 ? hs : 0.0f);
+        py = fmaf(thit, dy, ey) + (axis == 1 ? hs : 0.0f);
+        pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
+      }
+      if (phase != PH_IDLE) {
+        start_point<AXIS>(P, px, py, pz, h[0], z, q);
+        dl = trip + (uint32_t)N;
+      } else {
+        z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+        q = kNaN;
+        dl = trip + kIdleAhead;
+      }
+    }
+
+    if (__builtin_amdgcn_inverse_ballot_w64(fast)) {
+      k += 1.0f;
+      const float t = fmaf(k, dt, t0);
+      const float x = fmaf(t, dx, ex);
+      const float y = fmaf(t, dy, ey);
+      const float w = fmaf(t, dz, ez);
+      if constexpr (AXIS) {
+        // First update in closed form.
+        float a0;
+        start_axis_q(x, y, w, h, c0c3, a0, z, q);
+        if constexpr (STICKY) {
+          // zeta_2 escapes whenever zeta_1 does: leave zeta_1 untested (a sample that
+          // escaped on it retires after the next update, as a parked one would).
+          dl = trip + (uint32_t)(N - 1);
+        } else {
+          // Test zeta_1. An escaped sample is parked on a state that escapes on the
+          // next update (escape index 1); with max_iter 1 an inside one is parked on
+          // NaN (never escapes) and retires on its deadline at the next trip.
+          const bool esc1 = fmaf(a0, a0, cdsq - q) > R2c;
+          a0 = esc1 ? 1e18f : (n_is_1 ? kNaN : a0);
+          dl = trip + (uint32_t)(N - 1) + ((esc1 || n_is_1) ? 1u : 0u);
+        }
+        z.a0 = a0;
+      } else {
+        start_point<AXIS>(F->P, x, y, w, h[0], z, q);
+        dl = trip + (uint32_t)N;
+      }
+    }
+
+    if (!__builtin_amdgcn_ballot_w64(phase != PH_IDLE)) break;
+    }
   }
   if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
 }
