@@ -107,6 +107,20 @@ def cpu_baseline(ps, target_s):
             "seconds": round(dt, 2)}
 
 
+def cpu_one_thread_c1():
+    """The FP64 oracle on one thread over the whole 128x128 plain frame (seed 0: max_iter 12,
+    128 march steps, 8 bisection steps), the small configuration it finishes in a second."""
+    import oracle
+    import workloads
+    p = workloads.plain_128(0)[0]
+    t = time.perf_counter()
+    it = oracle.render(p, nthreads=1)["total_iters"]
+    dt = time.perf_counter() - t
+    return {"value": it / dt, "unit": "Julia iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole plain_128 frame, seed 0 ({p.pixels} rays, {it} updates, {dt:.2f} s, FP64)",
+            "seconds": round(dt, 3)}
+
+
 def _pct(xs, q):
     import numpy as np
     return float(np.quantile(np.asarray(xs), q)) if len(xs) else None
@@ -769,6 +783,7 @@ def main():
                                     args.serve_slots)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
+        line["cpu_baseline"]["one_thread_plain_128"] = cpu_one_thread_c1()
     if args.kernel == "refill":
         plan.close()
     print(json.dumps(line), flush=True)
