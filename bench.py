@@ -31,13 +31,11 @@ FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak
 # 1.196 ns per SIMD x 1024 SIMDs (profiles/gfx950_valu_issue.md).
 FP32_FMAC_ISSUE_TFLOPS = 109.6
 
-# HBM traffic of the timed plain_1024 kernel from two rocprofv3 --pmc runs (FETCH_SIZE and
-# WRITE_SIZE per dispatch, each scaled by what the counter reads for a 256 MiB device copy;
-# profiles/render_refill_plain_1024.md). It belongs to the kernel sources it was measured
-# on: bench.py reports it only while their hash is unchanged, else null.
-# HBM bytes per launch of the timed kernels, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
-# each scaled by what the counter reads for a 256 MiB device copy; valid while the hash of
-# the kernel's sources matches (else the bench line reports null).
+# HBM bytes per launch of the timed kernels, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+# (mean per dispatch), each scaled by what the counter reads for a 256 MiB device copy
+# (profiles/render_refill_plain_1024.md, profiles/classify_grid_voxel_1024.md). A record
+# belongs to the kernel sources it was measured on: bench.py reports it only while their
+# hash is unchanged, else null.
 TRAFFIC_RECORDS = {
     "plain": {
         "sources": ["paper_2303_14827_amd/csrc/render_refill.hip", "paper_2303_14827_amd/csrc/persist.h",
@@ -46,8 +44,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "06c823f00aca90080aefa4b3b9c9ac73074ddf38c290ba40208b5abc8c7d8cdb",
-        "fetch_kib": 69.21, "fetch_factor": 2.0, "write_kib": 37560.08, "write_factor": 1.0,
+        "sources_sha256": "8534e2266d894079e1c2bc52bb0bbf7ff0e999544739a9af3c9312faebf690e0",
+        "fetch_kib": 91.52, "fetch_factor": 2.0, "write_kib": 37823.77, "write_factor": 1.0,
     },
     "voxel": {
         "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
@@ -55,8 +53,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "66fdc1be5fcb0d86dba77ac9b17c83b9435e00e66e22fa72157636dc2838838f",
-        "fetch_kib": 1535.69, "fetch_factor": 2.0, "write_kib": 2789619.70, "write_factor": 1.0,
+        "sources_sha256": "015ee79f2968fe3732d0a4ae5ea5256bc45c03bac1e7c907d4df7dffe4aad31d",
+        "fetch_kib": 1540.94, "fetch_factor": 2.0, "write_kib": 2798018.39, "write_factor": 1.0,
     },
 }
 

@@ -229,3 +229,36 @@ def test_de_count_off_same_image(dqj):
         assert int(x["iters"].item()) > 0 and int(u["iters"].item()) == int(x["iters"].item())
         for k in ("mask", "depth", "shade"):
             assert torch.equal(x[k], y[k]) and torch.equal(x[k], u[k]) and torch.equal(x[k], v[k]), k
+
+
+def test_de_batch_spill_matches_single(dqj):
+    """Full-size DE frames, where the batch kernel hands the marches of each wave's last
+    rays to its resume kernel, and a batch of mixed sizes: every output (counts included)
+    equals the single renders' bit for bit, over graph replays too."""
+    import torch
+    big = workloads.de_1024()
+    mixed = [big[1].replace(width=97, height=61), big[0].replace(width=300, height=200),
+             big[2].replace(width=1, height=1), big[2]]
+    for p in mixed:
+        p.__post_init__()
+    for name, ps in (("de_1024", big), ("mixed", mixed)):
+        say("batch", name, [(p.width, p.height) for p in ps])
+        singles = [render(dqj, p) for p in ps]
+        outs = dqj.render_batch(ps, extras=True)
+        torch.cuda.synchronize()
+        for f, (o, g) in enumerate(zip(outs, singles)):
+            o = to_numpy(o)
+            for k in ("mask", "depth", "shade", "normal", "first_hit", "flags", "iters"):
+                np.testing.assert_array_equal(o[k], g[k], err_msg=f"{name} frame {f} {k}")
+        timed = [{k: v for k, v in dqj.alloc_outputs(p.width, p.height, extras=False).items()
+                  if k != "iters"} for p in ps]
+        plan = dqj.BatchPlan(ps, timed)
+        for rep in range(2):
+            for o in timed:
+                o["depth"].fill_(-1.0)
+            plan.launch()
+            torch.cuda.synchronize()
+            for f, (o, g) in enumerate(zip(timed, singles)):
+                for k in ("mask", "depth", "shade"):
+                    np.testing.assert_array_equal(o[k].cpu().numpy(), g[k], err_msg=f"{name} replay {rep} frame {f} {k}")
+        plan.close()
