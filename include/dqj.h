@@ -169,7 +169,8 @@ dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): dqj_render with the same arguments,
  * outputs and results, except that it allocates nothing. dqj_render keeps its tile
- * counter, and for split renders the candidate and FP64 ray lists, in device blocks it
+ * counter, and for split renders the candidate and FP64 ray lists with the candidates'
+ * chunk list, in device blocks it
  * allocates per (device, stream) on first use; this entry point keeps them instead in
  * one fixed device array of DQJ_NOALLOC_SCRATCH_BYTES per GPU, held from the library's
  * first call on that GPU until the process ends. The array bounds the split frames it
@@ -178,8 +179,8 @@ dqj_status dqj_render(const dqj_params *params, const dqj_frame_out *out, void *
  * clears what it needs with a kernel of its own, never a memset), so calls that overlap
  * on one GPU -- on two streams, or from two threads -- race and must be serialised by
  * the caller; calls in one stream's order are safe. */
-#define DQJ_NOALLOC_MAX_SPLIT_PIXELS 524288u
-#define DQJ_NOALLOC_SCRATCH_BYTES (256u + 32u * DQJ_NOALLOC_MAX_SPLIT_PIXELS)
+#define DQJ_NOALLOC_MAX_SPLIT_PIXELS 262144u
+#define DQJ_NOALLOC_SCRATCH_BYTES (256u + 48u * DQJ_NOALLOC_MAX_SPLIT_PIXELS)
 dqj_status dqj_render_noalloc(const dqj_params *params, const dqj_frame_out *out,
                               void *hip_stream);
 

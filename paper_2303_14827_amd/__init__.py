@@ -28,7 +28,7 @@ NORM_EUCLID8, NORM_REALPART = 0, 1
 PREC_FP32, PREC_SPLIT, PREC_FP64 = 0, 1, 2
 KERNEL_AUTO, KERNEL_REFILL, KERNEL_DIRECT, KERNEL_LOCKSTEP = 0, 1, 2, 3
 FLAG_BOX, FLAG_HIT, FLAG_FP64, FLAG_FALLBACK = 1, 2, 4, 8
-NOALLOC_MAX_SPLIT_PIXELS = 524288   # DQJ_NOALLOC_MAX_SPLIT_PIXELS
+NOALLOC_MAX_SPLIT_PIXELS = 262144   # DQJ_NOALLOC_MAX_SPLIT_PIXELS
 
 
 class DQJError(RuntimeError):

@@ -18,16 +18,27 @@ struct SplitEntry {
   int32_t kend;
 };
 
-// Device scratch of one split launch: ctr[0] tile counter, ctr[1] hit-list length,
-// ctr[2] ambiguous-list length; each list holds up to one entry per pixel.
+// A run of consecutive candidate-list entries of one frame (the FP16 march writes its
+// candidates in such chunks; the FP32 pass takes a chunk at a time).
+struct SplitChunk {
+  uint32_t frame;
+  uint32_t base;
+  uint32_t count;
+  uint32_t pad;
+};
+
+// Device scratch of one split launch: ctr[0] tile counter, ctr[1] candidate-list length,
+// ctr[2] FP64-list length, ctr[3] chunk count, ctr[4] chunks taken by the FP32 pass. The
+// lists hold up to one entry per pixel, the chunk array up to one chunk per entry.
 struct SplitScratch {
   uint32_t *ctr;
   SplitEntry *hits;
   SplitEntry *amb;
+  SplitChunk *chunks;
 };
 
 constexpr size_t split_scratch_bytes(uint64_t pixels) {
-  return 256 + 2 * sizeof(SplitEntry) * (size_t)pixels;
+  return 256 + (2 * sizeof(SplitEntry) + sizeof(SplitChunk)) * (size_t)pixels;
 }
 
 inline SplitScratch split_scratch_at(void *base, uint64_t pixels) {
@@ -35,6 +46,7 @@ inline SplitScratch split_scratch_at(void *base, uint64_t pixels) {
   s.ctr = (uint32_t *)base;
   s.hits = (SplitEntry *)((char *)base + 256);
   s.amb = s.hits + pixels;
+  s.chunks = (SplitChunk *)(s.amb + pixels);
   return s;
 }
 

@@ -236,6 +236,22 @@ __device__ __forceinline__ void wave_add_by_frame(int f, unsigned long long v, F
   }
 }
 
+// Write a wave's staged candidates (all lanes call it): reserve n list entries and one
+// chunk descriptor, copy the entries, describe the chunk.
+__device__ __forceinline__ void flush_stage(const SplitEntry *stage, int n, int frame,
+                                            uint32_t *ctr, SplitEntry *hits, SplitChunk *chunks,
+                                            int lane) {
+  uint32_t base = 0, cidx = 0;
+  if (lane == 0) {
+    base = atomicAdd(ctr + 1, (uint32_t)n);
+    cidx = atomicAdd(ctr + 3, 1u);
+  }
+  base = uniform((uint32_t)__shfl((int)base, 0, 64));
+  cidx = uniform((uint32_t)__shfl((int)cidx, 0, 64));
+  if (lane < n) hits[base + lane] = stage[lane];
+  if (lane == 0) chunks[cidx] = SplitChunk{(uint32_t)frame, base, (uint32_t)n, 0u};
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -247,10 +263,16 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
                                                           const LaunchHeader *__restrict__ hdr,
                                                           int nframes, uint32_t total_tiles,
                                                           uint32_t *__restrict__ ctr,
-                                                          SplitEntry *__restrict__ hits, int TW,
+                                                          SplitEntry *__restrict__ hits,
+                                                          SplitChunk *__restrict__ chunks, int TW,
                                                           int TH) {
   const int lane = lane_id();
   const int tile_rays = TW * TH;
+  // Candidates are staged per wave in LDS and written in chunks of up to 64 entries of
+  // one frame, one counter update per chunk (the FP32 pass takes whole chunks).
+  extern __shared__ SplitEntry split_stage[];
+  SplitEntry *const stage = split_stage + (threadIdx.x >> 6) * 64;
+  int scnt = 0;   // entries staged (wave-uniform)
   if constexpr (BATCH) {
     if (hdr) {   // sizes of this launch from device memory (graph replays with new tables)
       nframes = (int)uniform(((ConstHeader)hdr)->nframes);
@@ -296,6 +318,8 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
   // the FP32 pass re-checks that range.
   float kcf = -1.0f, kcl = -1.0f;
   uint32_t cnt_lo = 0, cnt_hi = 0, it_lane = 0;
+  int emit = 0;                 // this lane's ray becomes a candidate this trip
+  int32_t e_kc = 0, e_kend = 0;
 
   for (;;) {
     ++trip;
@@ -343,14 +367,27 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
           kc = kcf >= 0.0f && (int32_t)kcf < khat ? (int32_t)kcf : khat;
           kend = -1;
         }
-        const uint32_t slot = atomicAdd(ctr + 1, 1u);
-        hits[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, kc, kend};
+        emit = 1;
+        e_kc = kc;
+        e_kend = kend;
       }
       busy = 0;
       z.a0 = z.a1 = z.a2 = z.a3 = z.b0 = z.b1 = z.b2 = z.b3 = kNaN2;
       s = kNaN2;
       m2 = hsplat(0.0f);
       dl = trip + kIdleAhead;
+    }
+    // stage this trip's candidates, writing out the staged chunk first if they do not fit
+    const uint64_t emit_m = __builtin_amdgcn_ballot_w64(emit != 0);
+    if (emit_m) {
+      const int ne = __popcll(emit_m);
+      if (scnt + ne > 64) {
+        flush_stage(stage, scnt, frame, ctr, hits, chunks, lane);
+        scnt = 0;
+      }
+      if (emit) stage[scnt + rank_in(emit_m)] = SplitEntry{(uint32_t)frame, (uint32_t)pix, e_kc, e_kend};
+      scnt += ne;
+      emit = 0;
     }
     // (the pair's test from before the slow path: the lanes it ended fail it too)
     if (__builtin_amdgcn_inverse_ballot_w64(both_m & ~last_m)) {
@@ -433,6 +470,10 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
         if (f != frame) {
           if (idle != ~0ull) break;
           if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
+          if (scnt > 0) {
+            flush_stage(stage, scnt, frame, ctr, hits, chunks, lane);
+            scnt = 0;
+          }
           it_lane = 0;
           frame = f;
           if constexpr (BATCH) F = ctable + (int)uniform((uint32_t)f);
@@ -501,85 +542,294 @@ __global__ __launch_bounds__(1024) void march_fp16_kernel(FrameDesc single,
     }
     if (exhausted && !__builtin_amdgcn_ballot_w64(busy != 0)) break;
   }
+  if (scnt > 0) flush_stage(stage, scnt, frame, ctr, hits, chunks, lane);
   if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it_lane);
 }
 
 // ---------------------------------------------------------------------------
 // 2. FP32 pass over the candidate list
 // ---------------------------------------------------------------------------
-// One lane per listed ray: FP32 samples k = max(khat - w, 0), ... up to the first inside
-// one, k32 (to the last sample when the FP16 march found an inside sample, else to
-// kend + w: past that range every sample escaped within T16 FP16 updates). If the scan
-// starts inside (k32 = khat - w > 0), the crossing lies before it; if a sample of
-// k32 + 1 .. k32 + w is outside, the FP32 classes flip within the window. Both go to
-// the FP64 list. Otherwise bisect [t(k32 - 1), t(k32)] in FP32, take the normal and shade.
-// Waves take 64 consecutive entries per step, so their lanes meet at the end of every
-// step for the work-counter reduction.
-template <int NORM, bool BATCH, bool COUNT>
+// Persistent waves take the FP16 march's chunks (runs of up to 64 entries of one frame)
+// and hand their entries to idle lanes, as the FP32 marcher hands out tiles: the frame's
+// constants stay wave-uniform, and a wave starts another frame's chunk only once its
+// lanes are idle. Each lane walks its ray one update per trip:
+//   SCAN   : FP32 samples k = ks, ks + 1, ... with ks = max(khat - w, 0), up to the first
+//            inside one, k32 (to the last sample when the FP16 march found an inside
+//            sample, else to kend + w: past that range every sample escaped within T16
+//            FP16 updates; past it the ray misses). If sample ks > 0 is already inside,
+//            the crossing lies before the scan: FP64 list.
+//   CHECK  : samples k32 + 1 .. k32 + w (those up to S); an outside one means the FP32
+//            in/out test flips within the window: FP64 list.
+//   BISECT : B bisection points of [t(k32 - 1), t(k32)] (none when k32 = 0);
+//   NORMAL : the 6 central-difference points, then shade and write the pixel.
+// The update is the FP32 marcher's (q form; a scan sample's first update in closed form
+// on the identity slice).
+enum { VP_IDLE = 0, VP_SCAN = 1, VP_CHECK = 2, VP_BISECT = 3, VP_NORMAL = 4 };
+
+template <int NORM, bool AXIS, bool BATCH, bool COUNT>
 __global__ __launch_bounds__(256) void verify_fp32_kernel(FrameDesc single,
                                                           const FrameDesc *__restrict__ table,
                                                           uint32_t *__restrict__ ctr,
                                                           const SplitEntry *__restrict__ hits,
-                                                          SplitEntry *__restrict__ amb) {
+                                                          SplitEntry *__restrict__ amb,
+                                                          const SplitChunk *__restrict__ chunks) {
+  const int lane = lane_id();
   const ConstFrame ctable = (ConstFrame)table;
-  const uint32_t n = ctr[1];
-  const uint32_t wave0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = wave0; base < n; base += stride) {
-    const uint32_t e = base + (threadIdx.x & 63u);
-    uint32_t it = 0;
-    int fr = -1;
-    typename FramePtr<BATCH>::type F;
-    if constexpr (BATCH)
-      F = ctable;
-    else
-      F = &single;
-    if (e < n) {
-      const SplitEntry en = hits[e];
-      if constexpr (BATCH) F = ctable + en.frame;
-      fr = (int)en.frame;
+  const uint32_t nchunks = uniform(ctr[3]);
+  const float kNaN = __builtin_nanf("");
+  const float kNoMarch = 1e30f;
+  const uint32_t kIdleAhead = 0x7FFFFFFFu;
+
+  // ---- wave-uniform state: the frame and the chunk being handed out
+  typename FramePtr<BATCH>::type F;
+  if constexpr (BATCH)
+    F = nullptr;
+  else
+    F = &single;
+  int frame = -1;
+  bool pending = false, exhausted = false;
+  uint32_t pend_c = 0, ccount = 0;
+  int next_r = 0;
+  // per-lane copies of the frame's constants (see the FP32 marcher)
+  float h[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) h[i] = 0.0f;
+  float R2c = 0.0f, c0c3 = 0.0f, cdsq = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  int N = 1, S = 0, B = 0, w = 1;
+  // the chunk's entries: lane i holds entry i
+  int e_pix = 0, e_kc = 0, e_kend = 0;
+
+  // ---- per-lane ray state; idle lanes sit on a NaN state with a far deadline
+  int phase = VP_IDLE;
+  DQ<float> z{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+  float q = kNaN;
+  uint32_t trip = 0, dl = kIdleAhead;
+  int pix = 0, ks = 0, k32 = 0, j = 0, b = 0, sidx = 0;
+  float dx = 0, dy = 0, dz = 0, t0 = 0, dt = 0, k = kNoMarch, klh = 0.0f;
+  float lo = 0, hi = 0, thit = 0, gx = 0, gy = 0, gz = 0;
+  uint32_t it = 0;
+
+  enter_update_mode();
+  for (;;) {
+    ++trip;
+    const float n2 = dq_update_q<NORM>(z, q, h);
+    const bool esc = n2 > R2c;
+    const bool fast = esc && phase == VP_SCAN && k < klh;   // k integer-valued: more scan samples
+    const bool slow = (esc || (int)(trip - dl) >= 0) && !fast;
+    if (slow) {
       const KParams &P = F->P;
-      const int i = (int)(en.pix % (uint32_t)P.W), j = (int)(en.pix / (uint32_t)P.W);
-      float d[3], t0, t1;
-      pixel_dir(P, i, j, d);
-      clip_box(P, d, t0, t1);   // the FP16 march found this ray's segment with the same code
-      const float dt = (t1 - t0) / (float)P.S;
-      const int w = P.fp64_window, S = P.S;
-      const int ks = en.khat - w > 0 ? en.khat - w : 0;
-      const int klast = en.kend < 0 ? S : (en.kend + w < S ? en.kend + w : S);
-      int k32 = -1;
-      for (int k = ks; k <= klast; ++k) {
-        bool in;
-        float n2;
-        it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)k, dt, t0), d, 0.0f, 0.0f, 0.0f, &in,
-                               &n2);
-        if (in) {
-          k32 = k;
-          break;
+      const bool inside = !esc;
+      const int m = N - (int)(dl - trip);   // escape index, or N when inside
+      if (COUNT) it += (uint32_t)m;
+      bool start_hit = false, to_amb = false;
+      int amb_k = 0;
+      if (phase == VP_SCAN) {
+        if (!inside) {   // the scan's last sample escaped: the ray misses
+          write_pixel(F->out, pix, miss_pixel(DQJ_FLAG_BOX));
+          phase = VP_IDLE;
+        } else if ((int)k == ks && ks > 0) {
+          to_amb = true;
+          amb_k = ks;
+        } else {
+          k32 = (int)k;
+          j = 1;
+          phase = VP_CHECK;
+        }
+        k = kNoMarch;
+      } else if (phase == VP_CHECK) {
+        if (!inside) {
+          to_amb = true;
+          amb_k = k32;
+        } else {
+          ++j;
+        }
+      } else if (phase == VP_BISECT) {
+        const float tm = 0.5f * (lo + hi);
+        if (inside)
+          hi = tm;
+        else
+          lo = tm;
+        ++b;
+      } else {   // VP_NORMAL: stencil point sidx just retired
+        const float G = potential(n2 + h[0], m);
+        const float sg = (sidx & 1) ? -G : G;
+        const int axis = sidx >> 1;
+        if (axis == 0)
+          gx += sg;
+        else if (axis == 1)
+          gy += sg;
+        else
+          gz += sg;
+        ++sidx;
+      }
+      // the window after k32 is confirmed: bracket the crossing
+      if (phase == VP_CHECK && !to_amb && (j > w || k32 + j > S)) start_hit = true;
+      if (start_hit) {
+        b = 0;
+        if (k32 == 0) {
+          thit = t0;
+          phase = VP_NORMAL;
+        } else {
+          lo = fmaf((float)(k32 - 1), dt, t0);
+          hi = fmaf((float)k32, dt, t0);
+          phase = VP_BISECT;
         }
       }
-      bool to_fp64 = k32 == ks && ks > 0;
-      for (int jj = 1; k32 >= 0 && !to_fp64 && jj <= w && k32 + jj <= S; ++jj) {
-        bool in;
-        float n2;
-        it += classify_t<NORM>(P, P.c, P.N, P.R2, fmaf((float)(k32 + jj), dt, t0), d, 0.0f, 0.0f,
-                               0.0f, &in, &n2);
-        to_fp64 = !in;
+      if (phase == VP_BISECT && b >= B) {
+        thit = 0.5f * (lo + hi);
+        phase = VP_NORMAL;
       }
-      if (to_fp64) {
+      if (to_amb) {
         const uint32_t slot = atomicAdd(ctr + 2, 1u);
-        amb[slot] = SplitEntry{en.frame, en.pix, (int32_t)k32, -1};
-      } else if (k32 < 0) {
-        write_pixel(F->out, en.pix, miss_pixel(DQJ_FLAG_BOX));
-      } else {
+        amb[slot] = SplitEntry{(uint32_t)frame, (uint32_t)pix, (int32_t)amb_k, -1};
+        phase = VP_IDLE;
+      }
+      if (phase == VP_NORMAL && sidx == 6) {
+        const float g[3] = {gx, gy, gz};
+        const float d[3] = {dx, dy, dz};
         PixelOut r;
-        it += finish_ray<NORM>(P, P.c, P.N, P.B, P.R2, P.h, d, t0, dt, k32,
-                               (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
-        write_pixel(F->out, en.pix, r);
+        finish_hit(P, g, d, thit, k32, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
+        write_pixel(F->out, pix, r);
+        phase = VP_IDLE;
+      }
+      float px = 0, py = 0, pz = 0;
+      if (phase == VP_CHECK || phase == VP_BISECT) {
+        const float tr = phase == VP_CHECK ? fmaf((float)(k32 + j), dt, t0) : 0.5f * (lo + hi);
+        px = fmaf(tr, dx, ex);
+        py = fmaf(tr, dy, ey);
+        pz = fmaf(tr, dz, ez);
+      } else if (phase == VP_NORMAL) {
+        const int axis = sidx >> 1;
+        const float hs = (sidx & 1) ? -P.h : P.h;
+        px = fmaf(thit, dx, ex) + (axis == 0 ? hs : 0.0f);
+        py = fmaf(thit, dy, ey) + (axis == 1 ? hs : 0.0f);
+        pz = fmaf(thit, dz, ez) + (axis == 2 ? hs : 0.0f);
+      }
+      if (phase != VP_IDLE) {
+        if (AXIS)
+          z = DQ<float>{px, py, pz, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        else
+          z = slice_map<float>(P, px, py, pz);
+        q = q_of(z, h[0]);
+        dl = trip + (uint32_t)N;
+      } else {
+        z = DQ<float>{kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN, kNaN};
+        q = kNaN;
+        dl = trip + kIdleAhead;
       }
     }
-    if (COUNT) wave_add_by_frame(fr, it, F);
+    if (fast) {   // the next scan sample
+      if (COUNT) it += (uint32_t)N - (dl - trip);
+      k += 1.0f;
+      const float t = fmaf(k, dt, t0);
+      const float x = fmaf(t, dx, ex);
+      const float y = fmaf(t, dy, ey);
+      const float wz = fmaf(t, dz, ez);
+      if constexpr (AXIS) {
+        float a0;
+        start_axis_q(x, y, wz, h, c0c3, a0, z, q);
+        // zeta_1 is tested: an escaped sample is parked on a state that escapes on the
+        // next update; with max_iter 1 an inside one is parked on NaN
+        const bool esc1 = fmaf(a0, a0, cdsq - q) > R2c;
+        const bool n1 = N == 1;
+        z.a0 = esc1 ? 1e18f : (n1 ? kNaN : a0);
+        dl = trip + (uint32_t)(N - 1) + ((esc1 || n1) ? 1u : 0u);
+      } else {
+        z = slice_map<float>(F->P, x, y, wz);
+        q = q_of(z, h[0]);
+        dl = trip + (uint32_t)N;
+      }
+    }
+
+    // ---- hand the chunk's entries to idle lanes
+    uint64_t idle = __builtin_amdgcn_ballot_w64(phase == VP_IDLE);
+    while (idle) {
+      if (next_r >= (int)ccount) {   // the chunk is handed out: take the next one
+        if (exhausted) break;
+        if (!pending) {
+          uint32_t c = 0;
+          if (lane == 0) c = atomicAdd(ctr + 4, 1u);
+          c = uniform((uint32_t)__shfl((int)c, 0, 64));
+          if (c >= nchunks) {
+            exhausted = true;
+            break;
+          }
+          pend_c = c;
+          pending = true;
+        }
+        const int f = (int)uniform(chunks[pend_c].frame);
+        if (f != frame) {
+          if (idle != ~0ull) break;   // finish this frame's rays first
+          if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it);
+          it = 0;
+          frame = f;
+          if constexpr (BATCH) F = ctable + f;
+          const KParams &P = F->P;
+          float c[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) c[i] = uniform_f(P.c[i]);
+          h[0] = to_vgpr(c[0]);
+#pragma unroll
+          for (int i = 1; i < 8; ++i) h[i] = to_vgpr(uniform_f(0.5f * c[i]));
+          R2c = to_vgpr(uniform_f(P.R2 - c[0]));
+          c0c3 = to_vgpr(uniform_f(fmaf(-c[3], c[3], c[0])));
+          cdsq = NORM == 0 ? uniform_f(fmaf(c[7], c[7], fmaf(c[6], c[6], fmaf(c[5], c[5], c[4] * c[4]))))
+                           : 0.0f;
+          ex = to_vgpr(uniform_f(P.eye[0]));
+          ey = to_vgpr(uniform_f(P.eye[1]));
+          ez = to_vgpr(uniform_f(P.eye[2]));
+          N = (int)uniform((uint32_t)P.N);
+          S = (int)uniform((uint32_t)P.S);
+          B = (int)uniform((uint32_t)P.B);
+          w = (int)uniform((uint32_t)P.fp64_window);
+        }
+        const uint32_t cbase = uniform(chunks[pend_c].base);
+        ccount = uniform(chunks[pend_c].count);
+        pending = false;
+        next_r = 0;
+        if (lane < (int)ccount) {
+          const SplitEntry en = hits[cbase + lane];
+          e_pix = (int)en.pix;
+          e_kc = en.khat;
+          e_kend = en.kend;
+        }
+      }
+      const int rank = rank_in(idle);
+      const int src = next_r + rank;
+      const int s_pix = __shfl(e_pix, src & 63, 64), s_kc = __shfl(e_kc, src & 63, 64),
+                s_kend = __shfl(e_kend, src & 63, 64);
+      if (phase == VP_IDLE && src < (int)ccount) {
+        const KParams &P = F->P;
+        pix = s_pix;
+        const int ii = pix % P.W, jj = pix / P.W;
+        float d[3], ta, tb;
+        pixel_dir(P, ii, jj, d);
+        clip_box(P, d, ta, tb);   // the FP16 march found this ray's segment with the same code
+        dx = d[0];
+        dy = d[1];
+        dz = d[2];
+        t0 = ta;
+        dt = (tb - ta) / (float)S;
+        ks = s_kc - w > 0 ? s_kc - w : 0;
+        const int klast = s_kend < 0 ? S : (s_kend + w < S ? s_kend + w : S);
+        klh = (float)klast - 0.5f;
+        // enter as if sample ks - 1 had just escaped: the fast path starts sample ks
+        k = (float)(ks - 1);
+        phase = VP_SCAN;
+        sidx = P.normal_mode != 0 ? 6 : 0;
+        gx = gy = gz = 0.0f;
+        z = DQ<float>{1e18f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        q = 0.0f;
+        dl = trip + (uint32_t)N;
+        if (COUNT) it -= 1u;
+      }
+      const int cnt = __popcll(idle), avail = (int)ccount - next_r;
+      next_r += cnt < avail ? cnt : avail;
+      idle = __builtin_amdgcn_ballot_w64(phase == VP_IDLE);
+    }
+    if (exhausted && !__builtin_amdgcn_ballot_w64(phase != VP_IDLE)) break;
   }
+  if (COUNT && frame >= 0 && F->out.iters) wave_add_u64(F->out.iters, it);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,7 +904,7 @@ __global__ __launch_bounds__(256) void rebisect_fp64_kernel(FrameDesc single,
 }
 
 __global__ void reset_split_counters_kernel(uint32_t *ctr) {
-  if (threadIdx.x < 4) ctr[threadIdx.x] = 0u;
+  if (threadIdx.x < 8) ctr[threadIdx.x] = 0u;
 }
 
 template <bool BATCH, bool COUNT>
@@ -664,10 +914,11 @@ static void launch_split_variant(const FrameDesc &single, const FrameDesc *table
                                  const Sched &s, int cus, hipStream_t stream) {
   const int threads = 64 * s.waves_per_block;
   const int blocks = cus * s.blocks_per_cu;
+  const size_t stage_lds = sizeof(SplitEntry) * 64 * (size_t)s.waves_per_block;
 #define DQJ_MARCH(NM, AX)                                                                     \
-  hipLaunchKernelGGL((march_fp16_kernel<NM, AX, BATCH, COUNT>), dim3(blocks), dim3(threads), 0, \
-                     stream, single, table, hdr, nframes, total_tiles, sc.ctr, sc.hits, s.tile_w, \
-                     s.tile_h)
+  hipLaunchKernelGGL((march_fp16_kernel<NM, AX, BATCH, COUNT>), dim3(blocks), dim3(threads),  \
+                     stage_lds, stream, single, table, hdr, nframes, total_tiles, sc.ctr, sc.hits, \
+                     sc.chunks, s.tile_w, s.tile_h)
   if (norm == 0) {
     if (axis)
       DQJ_MARCH(0, true);
@@ -681,15 +932,23 @@ static void launch_split_variant(const FrameDesc &single, const FrameDesc *table
   }
 #undef DQJ_MARCH
   const int vblocks = cus * 8;
-#define DQJ_VERIFY(NM)                                                                            \
-  hipLaunchKernelGGL((verify_fp32_kernel<NM, BATCH, COUNT>), dim3(vblocks), dim3(256), 0,          \
-                     stream, single, table, sc.ctr, sc.hits, sc.amb);                               \
+#define DQJ_VERIFY(NM, AX)                                                                      \
+  hipLaunchKernelGGL((verify_fp32_kernel<NM, AX, BATCH, COUNT>), dim3(vblocks), dim3(256), 0,    \
+                     stream, single, table, sc.ctr, sc.hits, sc.amb, sc.chunks);                  \
   hipLaunchKernelGGL((rebisect_fp64_kernel<NM, BATCH, COUNT>), dim3(cus * 2), dim3(256), 0, stream, \
                      single, table, sc.ctr + 2, sc.amb)
   if (norm == 0) {
-    DQJ_VERIFY(0);
+    if (axis) {
+      DQJ_VERIFY(0, true);
+    } else {
+      DQJ_VERIFY(0, false);
+    }
   } else {
-    DQJ_VERIFY(1);
+    if (axis) {
+      DQJ_VERIFY(1, true);
+    } else {
+      DQJ_VERIFY(1, false);
+    }
   }
 #undef DQJ_VERIFY
 }

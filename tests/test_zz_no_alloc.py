@@ -82,7 +82,7 @@ def test_noalloc_fp32(dqj):
 
 
 def test_noalloc_split(dqj):
-    big = workloads.split_1080p([3])[0].replace(width=1024, height=512)   # the largest split frame
+    big = workloads.split_1080p([3])[0].replace(width=512, height=512)   # the largest split frame
     small = workloads.split_1080p([5])[0].replace(width=200, height=120)
     for p in (big, small):
         p.__post_init__()
@@ -101,7 +101,7 @@ def test_noalloc_distance_estimate(dqj):
 def test_noalloc_rejects_split_beyond_limit(dqj):
     """A split frame over the limit is refused on the host, before any launch."""
     import torch
-    p = workloads.split_1080p([0])[0].replace(width=1024, height=513)
+    p = workloads.split_1080p([0])[0].replace(width=512, height=513)
     p.__post_init__()
     out = dqj.alloc_outputs(p.width, p.height)
     sp = dqj.make_params(p)
