@@ -119,6 +119,11 @@ def cpu_one_thread_c1():
             "seconds": round(dt, 3)}
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def _pct(xs, q):
     import numpy as np
     return float(np.quantile(np.asarray(xs), q)) if len(xs) else None
@@ -196,6 +201,9 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
                          "first_launch_wait": r["t_first_launch"] - r["t_admit"],
                          "run": r["t_done"] - r["t_first_launch"], "side": p.width,
                          "max_iter": p.max_iter})
+            if len(recs) % 2000 == 0:
+                progress(f"served ({'split' if precision == workloads.PREC_SPLIT else 'FP32'}): "
+                         f"{len(recs)} of {len(arrivals)} requests done")
             counters.append(out["iters"])   # summed once at the end, off the critical path
             pixels += p.pixels
             n += 1
@@ -227,6 +235,8 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
             t_end = time.monotonic()
             recs.append({"lat": t_end - t_arr, "queue_wait": t_start - t_arr, "render": t_end - t_start,
                          "side": p.width, "max_iter": p.max_iter})
+            if len(recs) % 2000 == 0:
+                progress(f"plain: {len(recs)} of {len(arrivals)} requests done")
             counters.append(out["iters"])
             pixels += p.pixels
         dur = time.monotonic() - start
@@ -239,6 +249,7 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
            "requests": len(stream),
            "policy": "oldest first" if policy == dqj.SERVE_OLDEST else "fair share",
            "slots": slots or 3}
+    progress(f"serve stream of {len(stream)} requests: split server, FP32 server, plain")
     sr, si, sp, sn, sdur, sst = served(stream, True)
     res["served"] = {"precision": "split (FP16 march, FP32 re-check and bisection, FP64 re-bisection)",
                      **_tail(sr, served_keys), "epochs": sst["epochs"]}
@@ -248,6 +259,7 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
     pr, pi, pp, pn, pdur = plain(stream, True)
     res["plain"] = {"precision": "FP32, one request at a time, FIFO",
                     **_tail(pr, ("queue_wait", "render"))}
+    progress(f"capacity: {capacity_n} requests back to back, each way")
     cap = stream[:capacity_n]
     cl, ci, cp, cn, cdur, _ = served(cap, False)
     gl, gi, gp, gn, gdur, _ = served(cap, False, workloads.PREC_FP32)
@@ -484,6 +496,7 @@ def bench_de(args, dqj, workloads, torch):
         "hits_per_frame": [int(o["mask"].sum().item()) for o in outs],
     }
     if not args.no_cpu:
+        progress("CPU baseline: the FP64 oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
     return line
 
@@ -541,6 +554,7 @@ def bench_project(args, dqj, workloads, torch):
         "hits_per_frame": [int(o["mask"].sum().item()) for o in outs],
     }
     if not args.no_cpu:
+        progress("CPU baseline: the FP64 oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
     return line
 
@@ -780,6 +794,7 @@ def main():
                                     dqj.SERVE_OLDEST if args.serve_policy == "oldest" else dqj.SERVE_FAIR,
                                     args.serve_slots)
     if not args.no_cpu:
+        progress("CPU baseline: the FP64 oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
         line["cpu_baseline"]["one_thread_plain_128"] = cpu_one_thread_c1()
     if args.kernel == "refill":
