@@ -42,6 +42,7 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/qform.h",
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/launch.h", "paper_2303_14827_amd/csrc/refill.h",
+                    "paper_2303_14827_amd/csrc/tile_order.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
         "sources_sha256": "8534e2266d894079e1c2bc52bb0bbf7ff0e999544739a9af3c9312faebf690e0",

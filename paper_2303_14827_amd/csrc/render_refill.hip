@@ -19,12 +19,14 @@
 // camera stay wave-uniform (scalar registers). Results do not depend on which
 // lane or wave computes a pixel: images are bit-identical under any schedule.
 // Once the queue has ended, launches without the update counter finish their rays in
-// a second loop that runs the same trip without the hand-out.
+// a second loop that runs the same trip without the hand-out. The launch's last frame
+// is handed out centre-out (tile_order.h), so its long rays start early.
 #include "dq_device.h"
 #include "launch.h"
 #include "persist.h"
 #include "qform.h"
 #include "refill.h"
+#include "tile_order.h"
 
 #include <cstring>
 
@@ -309,6 +311,13 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
                            : 0.0f;
         }
         tile_local = pend_tile - F->tile_begin + F->tile_offset;
+        // The launch's last entry goes centre-out when it holds a whole frame (the
+        // chunks of a split frame keep the plain order, so together they still cover it).
+        if (frame == nframes - 1 && F->tile_offset == 0) {
+          const int ty_n = (F->P.H + TH - 1) / TH;
+          if (F->ntiles == F->tiles_x * (uint32_t)ty_n)
+            tile_local = centre_out_tile(tile_local, (int)F->tiles_x, ty_n);
+        }
         pending = false;
         have_tile = true;
         next_r = 0;
