@@ -18,6 +18,7 @@
 #include "dq_device.h"
 #include "launch.h"
 #include "qform.h"
+#include "tile_order.h"
 
 namespace dqj {
 
@@ -200,12 +201,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void r
   __syncthreads();
   // Each wave renders a compact tile of 64 / L pixels (8 x 8, 8 x 4 or 4 x 4), whose rays
   // are more alike than a row's; the block's four waves form a 2 x 2 arrangement of them.
+  // Blocks go centre-out in dispatch order (tile_order.h): the long rays near the image
+  // centre start first, the short ones at the edge fill the launch's ramp-down (three
+  // 512^2 frames 7% faster, the same images).
   constexpr int kWaveW = L == 4 ? 4 : 8, kWaveH = 64 / L / kWaveW;
   const int sub = threadIdx.x & (L - 1);
   const int wave = threadIdx.x >> 6;
   const int pix = (threadIdx.x & 63) / L;
-  const int i = blockIdx.x * (2 * kWaveW) + (wave & 1) * kWaveW + pix % kWaveW;
-  const int j = blockIdx.y * (2 * kWaveH) + (wave >> 1) * kWaveH + pix / kWaveW;
+  const uint32_t t = centre_out_tile(blockIdx.y * gridDim.x + blockIdx.x, (int)gridDim.x, (int)gridDim.y);
+  const int bx = (int)(t % gridDim.x), by = (int)(t / gridDim.x);
+  const int i = bx * (2 * kWaveW) + (wave & 1) * kWaveW + pix % kWaveW;
+  const int j = by * (2 * kWaveH) + (wave >> 1) * kWaveH + pix / kWaveW;
   unsigned long long iters = 0;
   enter_update_mode();
   QC K;
