@@ -45,8 +45,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/tile_order.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "8534e2266d894079e1c2bc52bb0bbf7ff0e999544739a9af3c9312faebf690e0",
-        "fetch_kib": 91.52, "fetch_factor": 2.0, "write_kib": 37823.77, "write_factor": 1.0,
+        "sources_sha256": "9b20e6ad992b434a11027edb2b48e0ae3a8af8c341f6a0ac445da6eba1bdfb07",
+        "fetch_kib": 102.4, "fetch_factor": 2.0, "write_kib": 38188.38, "write_factor": 1.0,
     },
     "voxel": {
         "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
@@ -54,8 +54,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "015ee79f2968fe3732d0a4ae5ea5256bc45c03bac1e7c907d4df7dffe4aad31d",
-        "fetch_kib": 1540.94, "fetch_factor": 2.0, "write_kib": 2798018.39, "write_factor": 1.0,
+        "sources_sha256": "5f82f6c07c54f7dbbb6c08229591bcd8762c7058c205417aed11e46cea31bf10",
+        "fetch_kib": 630.85, "fetch_factor": 2.0, "write_kib": 1326248.75, "write_factor": 1.0,
     },
 }
 
