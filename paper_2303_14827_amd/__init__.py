@@ -185,6 +185,7 @@ _SIGS = {
     "dqj_classify_grid": (C.c_int32, [C.POINTER(dqj_params), C.c_int32, C.c_int32, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dqj_device_info_get": (C.c_int32, [C.c_int32, C.POINTER(dqj_device_info)]),
+    "dqj_measure_engine_clock": (C.c_int32, [C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "dqj_autotune": (C.c_int32, [C.POINTER(dqj_params), C.POINTER(dqj_frame_out), C.c_int32,
                                  C.c_char_p, C.POINTER(dqj_schedule)]),
     "dqj_serve_create": (C.c_int32, [C.POINTER(dqj_serve_config), C.POINTER(C.c_void_p)]),
@@ -596,6 +597,14 @@ def device_info(device: int = 0) -> Dict:
             "memory_clock_khz": d.memory_clock_khz, "total_mem_bytes": d.total_mem_bytes,
             "fp32_vector_peak_tflops": d.fp32_vector_peak_tflops,
             "fp32_unpacked_peak_tflops": d.fp32_unpacked_peak_tflops}
+
+
+def measure_engine_clock(seconds: float = 0.2, device: int = 0) -> float:
+    """Engine clock (MHz) the device sustains under an FP32 FMA load of about `seconds`
+    (dqj_measure_engine_clock, include/dqj_measure.h)."""
+    mhz = C.c_double(0.0)
+    _check(lib().dqj_measure_engine_clock(int(device), float(seconds), C.byref(mhz)))
+    return mhz.value
 
 
 def exported_symbols() -> List[str]:

@@ -1,7 +1,8 @@
-"""The C ABI library: it loads, exports every function include/dqj.h declares, its
+"""The C ABI library: it loads, exports every function include/*.h declares, its
 record layouts match the header, and validation rejects bad input before any
 device work (these run without a GPU)."""
 import ctypes as C
+import glob
 import os
 import re
 import subprocess
@@ -13,12 +14,15 @@ import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "dqj.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dqj_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(dqj_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
@@ -133,3 +137,12 @@ def test_projection_validation():
                dict(precision=workloads.PREC_SPLIT)):
         st, msg = _render_status(BASE.replace(fiber=ok, **kw))
         assert st == dqj.E_UNSUPPORTED and "projection" in msg, (kw, st, msg)
+
+
+def test_engine_clock_rejects_bad_arguments():
+    L = dqj.lib()
+    mhz = C.c_double(-1.0)
+    assert L.dqj_measure_engine_clock(0, 0.0, C.byref(mhz)) == dqj.E_INVALID
+    assert L.dqj_measure_engine_clock(0, 11.0, C.byref(mhz)) == dqj.E_INVALID
+    assert L.dqj_measure_engine_clock(0, 0.1, None) == dqj.E_INVALID
+    assert mhz.value == -1.0   # untouched on failure
