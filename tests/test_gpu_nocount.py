@@ -192,3 +192,33 @@ def test_nocount_sweep_plan(dqj):
             for k in ("mask", "depth", "shade"):
                 assert torch.equal(t[k], c[k]), f"replay {rep} frame {i} {k}"
     plan.close()
+
+
+def test_nocount_guided_chunks(dqj):
+    """A launch with many tiles per wave takes its tiles in guided chunks (a kernel
+    instantiation of its own): up to 8 consecutive tiles per atomic, falling to 1 near the
+    end, across frame ends. One wave per CU and 4 x 2 tiles bring 20 sweep frames to 640
+    tiles per wave, so every chunk size occurs; the outputs must equal the counting
+    plan's, which takes one tile at a time."""
+    import torch
+    ps = workloads.sweep_256(20, first_seed=3000)
+    counted = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
+    cplan = dqj.BatchPlan(ps, counted)
+    cplan.launch()
+    torch.cuda.synchronize()
+    cplan.close()
+    s = dqj.make_schedule(kernel=dqj.KERNEL_REFILL, tile_w=4, tile_h=2, waves_per_block=1,
+                          blocks_per_cu=1)
+    timed = [{k: v for k, v in dqj.alloc_outputs(p.width, p.height, extras=False).items()
+              if k != "iters"} for p in ps]
+    say("guided plan, 20 frames of 256^2, 4x2 tiles, one wave per CU")
+    plan = dqj.BatchPlan(ps, timed, schedule=s)
+    for rep in range(2):
+        for t in timed:
+            t["mask"].fill_(7)
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (t, c) in enumerate(zip(timed, counted)):
+            for k in ("mask", "depth", "shade"):
+                assert torch.equal(t[k], c[k]), f"replay {rep} frame {i} {k}"
+    plan.close()
