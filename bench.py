@@ -45,8 +45,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/tile_order.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "9b20e6ad992b434a11027edb2b48e0ae3a8af8c341f6a0ac445da6eba1bdfb07",
-        "fetch_kib": 102.4, "fetch_factor": 2.0, "write_kib": 38188.38, "write_factor": 1.0,
+        "sources_sha256": "bd54d0869bd7cecf23b359841c3a9436cca3a0b8764e0baa456c233149a719fa",
+        "fetch_kib": 102.77, "fetch_factor": 2.0, "write_kib": 38302.35, "write_factor": 1.0,
     },
     "voxel": {
         "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
