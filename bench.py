@@ -54,8 +54,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "5f82f6c07c54f7dbbb6c08229591bcd8762c7058c205417aed11e46cea31bf10",
-        "fetch_kib": 630.85, "fetch_factor": 2.0, "write_kib": 1326248.75, "write_factor": 1.0,
+        "sources_sha256": "f004a12f1126ca5e6419053308bd63f96dc1ac14ad08897bab7cf277a95b94b0",
+        "fetch_kib": 622.27, "fetch_factor": 2.0, "write_kib": 1341538.26, "write_factor": 1.0,
     },
 }
 

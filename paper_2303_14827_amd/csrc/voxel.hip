@@ -152,6 +152,9 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
 
   // wave-uniform hand-out state
   uint32_t chunk = 0, next_r = 0;
+  const uint32_t kNoChunk = 0xFFFFFFFFu;
+  const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+  uint32_t first_chunk = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   bool have_chunk = false, exhausted = false;
 
   // per-lane state: an idle lane sits on NaN (never escapes) with a far deadline
@@ -206,9 +209,15 @@ __global__ __launch_bounds__(1024) void classify_grid_kernel(GridDesc G, uint32_
       while (idle) {
         if (!have_chunk) {
           if (exhausted) break;
-          uint32_t t = 0;
-          if (lane == 0) t = atomicAdd(counter, 1u);
-          t = uniform(t);
+          // The first chunk of every wave comes without the counter (wave w takes chunk
+          // w), which then hands out chunks from nwaves on: at the start all waves would
+          // queue on one atomic (about 60-80 us of the launch on 1024^3).
+          uint32_t t = first_chunk;
+          if (t == kNoChunk) {
+            if (lane == 0) t = atomicAdd(counter, 1u);
+            t = uniform(t) + nwaves;
+          }
+          first_chunk = kNoChunk;
           if (t >= G.nchunks) {
             exhausted = true;
             break;
