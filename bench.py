@@ -45,8 +45,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/tile_order.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "bd54d0869bd7cecf23b359841c3a9436cca3a0b8764e0baa456c233149a719fa",
-        "fetch_kib": 102.77, "fetch_factor": 2.0, "write_kib": 38302.35, "write_factor": 1.0,
+        "sources_sha256": "4dfca0949c8edfba07450ff2288f56a5bdb05d378139c215cf9fc4c574ec323f",
+        "fetch_kib": 103.17, "fetch_factor": 2.0, "write_kib": 38192.5, "write_factor": 1.0,
     },
     "voxel": {
         "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
@@ -54,8 +54,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "f004a12f1126ca5e6419053308bd63f96dc1ac14ad08897bab7cf277a95b94b0",
-        "fetch_kib": 622.27, "fetch_factor": 2.0, "write_kib": 1341538.26, "write_factor": 1.0,
+        "sources_sha256": "1fb547a59e3418002507913e3bce63569d77e1fc6f8eb5eb14054f85da26c533",
+        "fetch_kib": 621.25, "fetch_factor": 2.0, "write_kib": 1334244.62, "write_factor": 1.0,
     },
 }
 
@@ -525,36 +525,44 @@ def bench_de(args, dqj, workloads, torch):
 
 def bench_project(args, dqj, workloads, torch):
     """Projection ("shadow") rendering: three 512x512 frames of the paper's constants,
-    each point's fibre sampled by 16 offsets (one dqj_render per frame; the projection
-    kernel with a group of 4 lanes per pixel), against the FP64 oracle's count of the
-    updates that render runs (tests/golden/ialg_project_512.json)."""
+    each point's fibre sampled by 16 offsets, as one graph-replayed batch launch (the
+    frames' blocks interleaved; 4 lanes per pixel), against the FP64 oracle's count of the
+    updates the render runs (tests/golden/ialg_project_512.json). The three frames as
+    single dqj_render launches are timed beside it."""
     ps = workloads.project_512()
     with open(os.path.join(ROOT, "tests", "golden", "ialg_project_512.json")) as f:
         ialg = json.load(f)["total_iters"]
     stream = torch.cuda.current_stream()
     outs = [dqj.alloc_outputs(p.width, p.height, extras=False) for p in ps]
-    for p, o in zip(ps, outs):
-        dqj.render(p, out=o, stream=stream)
+    cplan = dqj.BatchPlan(ps, outs)
+    cplan.launch()
     torch.cuda.synchronize()
+    cplan.close()
     counted = sum(int(o["iters"].item()) for o in outs)
     timed = [{k: v for k, v in o.items() if k != "iters"} for o in outs]
+    plan = dqj.BatchPlan(ps, timed)
 
-    def step():
+    def timed_loop(step, steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
+
+    ms, ev_ms = timed_loop(lambda: plan.launch(stream), args.steps, args.warmup)
+
+    def singles():
         for p, o in zip(ps, timed):
             dqj.render(p, out=o, stream=stream)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    ev_ms = e0.elapsed_time(e1) / args.steps
+    single_ms, _ = timed_loop(singles, max(1, args.steps // 4), 2)
+    plan.close()
     achieved = FLOPS_PER_UPDATE * ialg / (ev_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC, "value": ialg / (ms * 1e-3), "unit": "Julia iters/s", "n_gpus": 1,
@@ -563,12 +571,13 @@ def bench_project(args, dqj, workloads, torch):
         "config": {"workload": "project_512: 3 frames of 512x512, the shadows of the sets of "
                                "the paper's constants PAPER_C[7], [0], [4] (max_iter 15, 256 "
                                "march steps, 10 bisection steps), each fibre sampled by 16 "
-                               "offsets; one dqj_render per frame",
-                   "frames": 3, "width": 512, "height": 512, "max_iter": 15, "fibers": 16},
+                               "offsets; one graph-replayed batch launch per step",
+                   "frames": 3, "width": 512, "height": 512, "max_iter": 15, "fibers": 16,
+                   "single_launches_ms_per_step": single_ms},
         "pct_fp32_peak": 100.0 * achieved / FP32_PEAK_TFLOPS,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "render_project_kernel", "kernel_ms_per_step": ev_ms,
+                     "kernel": "render_project_batch_kernel", "kernel_ms_per_step": ev_ms,
                      "flops_per_update": FLOPS_PER_UPDATE,
                      "frac_of_measured_fmac_issue": achieved / FP32_FMAC_ISSUE_TFLOPS},
         "ialg_per_step": ialg, "ialg_source": "FP64 oracle, tests/golden/ialg_project_512.json",

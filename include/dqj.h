@@ -127,8 +127,10 @@ typedef struct dqj_params {
    * offsets in R^8, row-major F x 8, host memory read during the call). The offsets
    * sample the directions the projection collapses, so the image is the shadow of the
    * set sampled at those fibre points. The potential of the normal is the least of the F
-   * points' potentials. dqj_render only, FP32 fixed-step march with the dual square;
-   * other calls and modes return DQJ_E_UNSUPPORTED. 0: slice rendering. */
+   * points' potentials. dqj_render, dqj_render_batch and batch plans (a batch holds
+   * projection frames only, or none: DQJ_E_INVALID otherwise), FP32 fixed-step march with
+   * the dual square; the server, the autotuner and other modes return DQJ_E_UNSUPPORTED.
+   * 0: slice rendering. */
   int32_t fiber_count;         /* 0..32 */
   int32_t fiber_reserved;      /* 0 */
   const double *fiber;         /* fiber_count x 8 values; NULL when fiber_count = 0 */
@@ -185,7 +187,9 @@ dqj_status dqj_render_noalloc(const dqj_params *params, const dqj_frame_out *out
                               void *hip_stream);
 
 /* Render n frames (params[i] -> outs[i]) in one persistent launch over a global
- * (frame, tile) queue. All frames must share precision. */
+ * (frame, tile) queue. All frames must share precision, march and escape norm. A batch
+ * of projection frames (fiber_count > 0, all of them) runs one launch with the frames'
+ * blocks interleaved instead. */
 dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
                             void *hip_stream);
 

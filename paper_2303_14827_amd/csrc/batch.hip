@@ -17,6 +17,7 @@
 #include "launch.h"
 #include "refill.h"
 #include "split.h"
+#include "project.h"
 #include "runtime_internal.h"
 
 namespace dqj {
@@ -27,10 +28,11 @@ namespace {
 dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32_t n,
                       const Sched &s, std::vector<FrameDesc> &table, uint32_t &total_tiles,
                       int &norm, bool &all_axis, int &slice_mode, bool &any_count,
-                      int &precision, uint64_t &pixels) {
+                      int &precision, uint64_t &pixels, std::vector<ProjFiber> &fibers) {
   if (n < 1) return fail(DQJ_E_INVALID, "batch size must be >= 1 (got %d)", n);
   if (!params || !outs) return fail(DQJ_E_INVALID, "params and outs are required");
   table.resize(n);
+  fibers.clear();
   uint64_t tiles = 0;
   all_axis = true;
   slice_mode = kSliceIdentitySticky;
@@ -39,7 +41,17 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
   for (int32_t i = 0; i < n; ++i) {
     dqj_status st = validate_params(params + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
-    st = check_render_modes(params[i], false);
+    // A batch holds projection frames only, or none: they run a kernel of their own.
+    const bool proj = params[i].fiber_count > 0;
+    if (i > 0 && proj != (params[0].fiber_count > 0))
+      return fail(DQJ_E_INVALID, "frame %d: a batch holds projection frames only, or none", i);
+    if (proj) {
+      st = check_render_modes(params[i], true);   // FP32, fixed-step march
+      if (st == DQJ_OK && params[i].normal_mode == DQJ_NORMAL_NEIGHBOUR4)
+        st = fail(DQJ_E_UNSUPPORTED, "the four-neighbour normal is offered by dqj_render only");
+    } else {
+      st = check_render_modes(params[i], false);
+    }
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
     st = validate_out(outs + i);
     if (st != DQJ_OK) return fail(st, "frame %d: %s", i, dqj_last_error());
@@ -58,6 +70,14 @@ dqj_status pack_batch(const dqj_params *params, const dqj_frame_out *outs, int32
     pack_params(params[i], f.P);
     pack_params64(params[i], f.P64);
     f.out = to_kout(outs[i]);
+    if (proj) {
+      if (fibers.empty()) fibers.resize(n);
+      ProjFiber &pf = fibers[i];
+      memset(&pf, 0, sizeof pf);
+      pf.F = params[i].fiber_count;
+      for (int k = 0; k < pf.F; ++k)
+        for (int q = 0; q < 8; ++q) pf.off[k][q] = (float)params[i].fiber[8 * k + q];
+    }
     pixels += (uint64_t)params[i].width * (uint64_t)params[i].height;
     f.tile_begin = (uint32_t)tiles;
     set_tiles(f, s.tile_w, s.tile_h);
@@ -85,6 +105,22 @@ hipError_t launch_de_table(const FrameDesc *dev, const std::vector<FrameDesc> &t
     count = count || f.out.iters != nullptr;
   }
   return launch_render_de_batch(dev, (int)table.size(), mw, mh, norm, all_axis, count, s);
+}
+
+// A batch of projection frames: their fibre records follow the FrameDesc table in `dev`.
+hipError_t launch_project_table(const FrameDesc *dev, const std::vector<FrameDesc> &table,
+                                const std::vector<ProjFiber> &fibers, int norm, uint64_t pixels,
+                                hipStream_t s) {
+  int mw = 0, mh = 0, min_f = kMaxFiber;
+  bool count = false;
+  for (size_t i = 0; i < table.size(); ++i) {
+    mw = table[i].P.W > mw ? table[i].P.W : mw;
+    mh = table[i].P.H > mh ? table[i].P.H : mh;
+    min_f = fibers[i].F < min_f ? fibers[i].F : min_f;
+    count = count || table[i].out.iters != nullptr;
+  }
+  const ProjFiber *fdev = (const ProjFiber *)((const char *)dev + sizeof(FrameDesc) * table.size());
+  return launch_render_project_batch(dev, fdev, (int)table.size(), mw, mh, norm, count, pixels, min_f, s);
 }
 
 // Allocations an eager batch leaves behind until the stream has passed them.
@@ -161,23 +197,29 @@ dqj_status dqj_render_batch(const dqj_params *params, const dqj_frame_out *outs,
     int slice_mode = kSliceGeneral;
     int precision = 0;
     uint64_t pixels = 0;
+    std::vector<ProjFiber> fibers;
     st = pack_batch(params, outs, n, s, table, total, norm, all_axis, slice_mode, any_count, precision,
-                    pixels);
+                    pixels, fibers);
     if (st != DQJ_OK) return st;
     reap_retired(false);
     hipStream_t stream = (hipStream_t)hip_stream;
-    const size_t bytes = sizeof(FrameDesc) * table.size();
+    const size_t tbytes = sizeof(FrameDesc) * table.size();
+    const size_t bytes = tbytes + sizeof(ProjFiber) * fibers.size();
     Retired r{nullptr, nullptr, nullptr};
     hipError_t e = hipHostMalloc(&r.host, bytes, hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
-    memcpy(r.host, table.data(), bytes);
+    memcpy(r.host, table.data(), tbytes);
+    if (!fibers.empty()) memcpy((char *)r.host + tbytes, fibers.data(), bytes - tbytes);
     e = hipMalloc(&r.dev, bytes);
     if (e != hipSuccess) {
       (void)hipHostFree(r.host);
       return fail(DQJ_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
     e = hipMemcpyAsync(r.dev, r.host, bytes, hipMemcpyHostToDevice, stream);
-    if (table[0].P.march == DQJ_MARCH_DE) {
+    if (!fibers.empty()) {
+      if (e == hipSuccess)
+        e = launch_project_table((const FrameDesc *)r.dev, table, fibers, norm, pixels, stream);
+    } else if (table[0].P.march == DQJ_MARCH_DE) {
       if (e == hipSuccess) e = launch_de_table((const FrameDesc *)r.dev, table, norm, all_axis, stream);
     } else if (precision == DQJ_PREC_FP32) {
       uint32_t *counter = nullptr;
@@ -236,12 +278,14 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     int slice_mode = kSliceGeneral;
     int precision = 0;
     uint64_t pixels = 0;
+    std::vector<ProjFiber> fibers;
     st = pack_batch(params, outs, n, s, table, total, norm, all_axis, slice_mode, any_count, precision,
-                    pixels);
+                    pixels, fibers);
     if (st != DQJ_OK) return st;
     p = new dqj_batch_plan;
     p->dev = dev;
-    const size_t bytes = sizeof(FrameDesc) * table.size();
+    const size_t tbytes = sizeof(FrameDesc) * table.size();
+    const size_t bytes = tbytes + sizeof(ProjFiber) * fibers.size();
     hipError_t e = hipMalloc(&p->table_dev, bytes);
     if (e != hipSuccess) {
       plan_free(p);
@@ -250,14 +294,18 @@ dqj_status dqj_batch_plan_create(const dqj_params *params, const dqj_frame_out *
     e = hipMalloc(&p->counter_dev, 256);
     if (e == hipSuccess && precision == DQJ_PREC_SPLIT)
       e = hipMalloc(&p->split_scratch, split_scratch_bytes(pixels));
-    if (e == hipSuccess) e = hipMemcpy(p->table_dev, table.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->table_dev, table.data(), tbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !fibers.empty())
+      e = hipMemcpy((char *)p->table_dev + tbytes, fibers.data(), bytes - tbytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       // The capture holds a counter-reset kernel (not a memset node) and the kernel.
       hipError_t le =
-          table[0].P.march == DQJ_MARCH_DE
+          !fibers.empty()
+              ? launch_project_table(p->table_dev, table, fibers, norm, pixels, p->cap_stream)
+          : table[0].P.march == DQJ_MARCH_DE
               ? launch_de_table(p->table_dev, table, norm, all_axis, p->cap_stream)
           : precision == DQJ_PREC_FP32
               ? launch_render_refill_batch(p->table_dev, nullptr, n, total, norm, slice_mode, any_count,

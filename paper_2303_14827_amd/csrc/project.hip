@@ -17,7 +17,9 @@
 // sit in LDS, read per lane.
 #include "dq_device.h"
 #include "launch.h"
+#include "persist.h"
 #include "qform.h"
+#include "project.h"
 #include "tile_order.h"
 
 namespace dqj {
@@ -227,6 +229,74 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void r
   if constexpr (COUNT) wave_add_u64(out.iters, iters);
 }
 
+// Several projection frames in one launch. Block g of the launch renders block g / n of
+// frame g % n (the frames interleaved in dispatch order, so one frame's slow blocks overlap
+// the others' work), each frame's blocks taken centre-out; the fibre offsets come from the
+// frame's record in device memory. Otherwise the body is render_project_kernel's.
+template <int NORM, int L, bool COUNT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void render_project_batch_kernel(
+    const FrameDesc *__restrict__ table, const ProjFiber *__restrict__ fibers, uint32_t nf) {
+  constexpr int kWaveW = L == 4 ? 4 : 8, kWaveH = 64 / L / kWaveW;
+  const uint32_t g = blockIdx.x;
+  const uint32_t fi = g % nf;
+  const persist::ConstFrame Fd = (persist::ConstFrame)table + fi;
+  const KParams &P = Fd->P;
+  const int X = (P.W + 2 * kWaveW - 1) / (2 * kWaveW), Y = (P.H + 2 * kWaveH - 1) / (2 * kWaveH);
+  const uint32_t b = g / nf;
+  if (b >= (uint32_t)(X * Y)) return;   // a frame smaller than the largest (whole block)
+  const ProjFiber *pf = fibers + fi;
+  const int F = pf->F;
+  __shared__ FiberLds fl;
+  if ((int)threadIdx.x < F) {
+    const float *o = pf->off[threadIdx.x];
+    fl.off[threadIdx.x][0] = make_float4(o[0], o[1], o[2], o[3]);
+    fl.off[threadIdx.x][1] = make_float4(o[4], o[5], o[6], o[7]);
+  }
+  __syncthreads();
+  const int sub = threadIdx.x & (L - 1);
+  const int wave = threadIdx.x >> 6;
+  const int pix = (threadIdx.x & 63) / L;
+  const uint32_t t = centre_out_tile(b, X, Y);
+  const int bx = (int)(t % (uint32_t)X), by = (int)(t / (uint32_t)X);
+  const int i = bx * (2 * kWaveW) + (wave & 1) * kWaveW + pix % kWaveW;
+  const int j = by * (2 * kWaveH) + (wave >> 1) * kWaveH + pix / kWaveW;
+  unsigned long long iters = 0;
+  enter_update_mode();
+  QC K;
+  K.h[0] = to_vgpr(P.c[0]);
+#pragma unroll
+  for (int q = 1; q < 8; ++q) K.h[q] = to_vgpr(0.5f * P.c[q]);
+  K.R2c = to_vgpr(P.R2 - P.c[0]);
+  if (i < P.W && j < P.H) {
+    PixelOut r;
+    render_pixel_project<NORM, L, COUNT>(P, K, fl, F, sub, i, j, r, iters);
+    if (sub == 0) write_pixel(Fd->out, (int64_t)j * P.W + i, r);
+  }
+  if constexpr (COUNT) {
+    if (Fd->out.iters) wave_add_u64(Fd->out.iters, iters);
+  }
+}
+
+template <int L>
+void launch_batch_lanes(const FrameDesc *table, const ProjFiber *fibers, int n, int max_w, int max_h,
+                        int norm, bool count, hipStream_t s) {
+  constexpr int kWaveW = L == 4 ? 4 : 8, kWaveH = 64 / L / kWaveW;
+  const uint32_t per_frame = (uint32_t)(((max_w + 2 * kWaveW - 1) / (2 * kWaveW)) *
+                                        ((max_h + 2 * kWaveH - 1) / (2 * kWaveH)));
+  const dim3 grid(per_frame * (uint32_t)n);
+  if (norm == 0) {
+    if (count)
+      hipLaunchKernelGGL((render_project_batch_kernel<0, L, true>), grid, dim3(256), 0, s, table, fibers, (uint32_t)n);
+    else
+      hipLaunchKernelGGL((render_project_batch_kernel<0, L, false>), grid, dim3(256), 0, s, table, fibers, (uint32_t)n);
+  } else {
+    if (count)
+      hipLaunchKernelGGL((render_project_batch_kernel<1, L, true>), grid, dim3(256), 0, s, table, fibers, (uint32_t)n);
+    else
+      hipLaunchKernelGGL((render_project_batch_kernel<1, L, false>), grid, dim3(256), 0, s, table, fibers, (uint32_t)n);
+  }
+}
+
 // The counting kernels run only where the caller asked for the update count.
 template <int L>
 void launch_lanes(const KParams &P, const FiberTable &fb, int F, const KOut &out, hipStream_t s) {
@@ -259,6 +329,23 @@ int project_lanes(const KParams &P, int F) {
 }
 
 }  // namespace
+
+// Lanes per pixel for a batch: the least of 1, 2 and 4 that puts about 2^21 lanes in the
+// launch (its blocks overlap across frames, so more are in flight than in one frame's
+// launch), and at most the smallest F.
+hipError_t launch_render_project_batch(const FrameDesc *table_dev, const ProjFiber *fibers_dev,
+                                       int nframes, int max_w, int max_h, int norm, bool count,
+                                       uint64_t pixels, int min_fiber, hipStream_t s) {
+  if (nframes < 1 || min_fiber < 1 || min_fiber > kMaxFiber) return hipErrorInvalidValue;
+  int lanes = 1;
+  while (lanes < 4 && 2 * lanes <= min_fiber && pixels * (uint64_t)lanes < (uint64_t(1) << 21)) lanes *= 2;
+  switch (lanes) {
+    case 1: launch_batch_lanes<1>(table_dev, fibers_dev, nframes, max_w, max_h, norm, count, s); break;
+    case 2: launch_batch_lanes<2>(table_dev, fibers_dev, nframes, max_w, max_h, norm, count, s); break;
+    default: launch_batch_lanes<4>(table_dev, fibers_dev, nframes, max_w, max_h, norm, count, s); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_render_project(const KParams &P, const FiberTable &fb, int F, const KOut &out,
                                  hipStream_t s) {

@@ -174,7 +174,7 @@ dqj_status check_render_modes(const dqj_params &p, bool single) {
   if (p.algebra != DQJ_ALGEBRA_DUAL)
     return fail(DQJ_E_UNSUPPORTED, "the component-wise algebra is offered by dqj_classify_grid only");
   if (p.fiber_count > 0) {
-    if (!single) return fail(DQJ_E_UNSUPPORTED, "projection rendering is offered by dqj_render only");
+    if (!single) return fail(DQJ_E_UNSUPPORTED, "projection rendering is offered by dqj_render and batches only");
     if (p.precision != DQJ_PREC_FP32 || p.march != DQJ_MARCH_FIXED)
       return fail(DQJ_E_UNSUPPORTED, "projection rendering runs the FP32 fixed-step march");
   }

@@ -107,10 +107,63 @@ def test_neighbour_normal_projection(dqj, oracle_mod):
     assert_parity(rep, *BAR)
 
 
-def test_projection_refused_in_batches(dqj):
+PKEYS = ("mask", "depth", "shade", "normal", "first_hit", "image8", "flags")
+
+
+def test_projection_batch_equals_single(dqj):
+    """A batch of projection frames (one launch, the frames' blocks interleaved) and a
+    captured plan of the same frames give every frame bit for bit what dqj_render gives,
+    update counts included: frames of different sizes, fibre counts and constants."""
+    import torch
+    ps = [workloads.project_128(0)[0],
+          workloads.project_128(1, fibers=3)[0].replace(width=97, height=61),
+          workloads.project_128(2, fibers=16)[0].replace(width=160, height=120, c=workloads.PAPER_C[7],
+                                                        max_iter=15),
+          workloads.project_128(3, fibers=1)[0].replace(width=33, height=1)]
+    for p in ps:
+        p.__post_init__()
+    singles = []
+    for p in ps:
+        o = dqj.alloc_outputs(p.width, p.height)
+        dqj.render(p, out=o)
+        torch.cuda.synchronize()
+        singles.append((to_numpy(o), int(o["iters"].item())))
+    say("singles done", [s[1] for s in singles])
+    outs = [dqj.alloc_outputs(p.width, p.height) for p in ps]
+    dqj.render_batch(ps, outs)
+    torch.cuda.synchronize()
+    for i, (o, (a, it)) in enumerate(zip(outs, singles)):
+        g = to_numpy(o)
+        for k in PKEYS:
+            np.testing.assert_array_equal(g[k], a[k], err_msg=f"batch frame {i} {k}")
+        assert int(o["iters"].item()) == it, (i, int(o["iters"].item()), it)
+    say("batch equal")
+    outs2 = [{k: v for k, v in dqj.alloc_outputs(p.width, p.height).items() if k != "iters"} for p in ps]
+    plan = dqj.BatchPlan(ps, outs2)
+    for rep in range(2):
+        for o in outs2:
+            o["depth"].fill_(-1.0)
+        plan.launch()
+        torch.cuda.synchronize()
+        for i, (o, (a, _)) in enumerate(zip(outs2, singles)):
+            g = to_numpy(o)
+            for k in PKEYS:
+                np.testing.assert_array_equal(g[k], a[k], err_msg=f"plan replay {rep} frame {i} {k}")
+    plan.close()
+
+
+def test_projection_batch_refusals(dqj):
     p = workloads.project_128(0)[0]
-    with pytest.raises(Exception):
-        dqj.render_batch([p, p])
+    q = workloads.plain_128(0)[0]
+    with pytest.raises(Exception, match="projection frames only"):
+        dqj.render_batch([p, q])
+    with pytest.raises(Exception, match="projection frames only"):
+        dqj.render_batch([q, p])
+    with pytest.raises(Exception, match="four-neighbour"):
+        dqj.render_batch([p, p.replace(normal_mode=workloads.NORMAL_NEIGHBOUR4)])
+    with dqj.Server(precision=workloads.PREC_FP32) as srv:
+        with pytest.raises(Exception, match="projection"):
+            srv.submit(p.replace(precision=workloads.PREC_FP32), dqj.alloc_outputs(p.width, p.height))
 
 
 def test_project_512_sampled(dqj, oracle_mod):
