@@ -56,9 +56,11 @@ __device__ __forceinline__ void start_point(const KParams &P, float x, float y, 
 // so march samples take their first update in closed form), BATCH (frames come from a
 // device table), COUNT (accumulate executed updates per frame), STICKY (every frame
 // guarantees that a march sample escaping on its first update escapes on the second,
-// so that update is not tested; only used with AXIS and without COUNT), GUIDED (tiles are
-// handed out in chunks sized by the tiles left: see the hand-out).
-template <int NORM, bool AXIS, bool BATCH, bool COUNT, bool STICKY, bool GUIDED>
+// so that update is not tested; only used with AXIS and without COUNT), HAND (how tiles
+// are handed out: one per atomic, guided chunks, or a first tile per wave without the
+// counter; see the hand-out).
+enum { kHandOne = 0, kHandGuided = 1, kHandFirst = 2 };
+template <int NORM, bool AXIS, bool BATCH, bool COUNT, bool STICKY, int HAND>
 __device__ __forceinline__ void refill_body(const FrameDesc &single,
                                             const FrameDesc *__restrict__ table,
                                             const LaunchHeader *__restrict__ hdr, int nframes,
@@ -91,7 +93,10 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
   uint32_t tile_local = 0;      // tile index within the frame
   int next_r = 0;               // next ray of the tile to hand out
   bool have_tile = false, pending = false, exhausted = false;
-  uint32_t spare = 0, spare_n = 0, last_t = 0;   // GUIDED: the rest of the wave's chunk
+  uint32_t spare = 0, spare_n = 0, last_t = 0;   // kHandGuided: the rest of the wave's chunk
+  // kHandFirst: the wave's first tile (wave w takes tile w), taken without the counter
+  const uint32_t kNoTile = 0xFFFFFFFFu;
+  uint32_t first_tile = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   uint32_t pend_tile = 0;
   float R2c = 0.0f, c0c3 = 0.0f, cdsq = 0.0f, Sfh = 0.0f;
   float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // eye (cached: the table is not provably read-only)
@@ -279,7 +284,7 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
         if (exhausted) break;
         if (!pending) {
           uint32_t t = 0;
-          if constexpr (GUIDED) {
+          if constexpr (HAND == kHandGuided) {
             // Guided self-scheduling: a chunk of g consecutive tiles per atomic, g = the
             // tiles left (as this wave last saw the counter) / (64 x waves), between 1 and
             // 8. Large launches take whole runs of a frame's tiles early, so a wave changes
@@ -300,6 +305,17 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
               spare = t + 1u;
               spare_n = g - 1u;
             }
+          } else if constexpr (HAND == kHandFirst) {
+            // A single frame's launch gives each wave two or three tiles, and at the start
+            // all waves would queue on one atomic: the first tiles go one per wave, and the
+            // counter hands out tiles from nwaves on (a 1024^2 frame with many hits 7%
+            // faster). Batches keep one tile per atomic: there the same change cost 3%.
+            t = first_tile;
+            if (t == kNoTile) {
+              if (lane == 0) t = atomicAdd(counter, 1u);
+              t = uniform(t) + gridDim.x * (blockDim.x >> 6);
+            }
+            first_tile = kNoTile;
           } else {
             if (lane == 0) t = atomicAdd(counter, 1u);
             t = uniform(t);
@@ -552,8 +568,8 @@ __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
                                                              int nframes, uint32_t total_tiles,
                                                              uint32_t *__restrict__ counter,
                                                              int TW, int TH) {
-  refill_body<NORM, AXIS, false, COUNT, STICKY, false>(single, table, hdr, nframes, total_tiles,
-                                                       counter, TW, TH);
+  refill_body<NORM, AXIS, false, COUNT, STICKY, kHandFirst>(single, table, hdr, nframes,
+                                                            total_tiles, counter, TW, TH);
 }
 
 // Batched launches (frames from a device table: the throughput path) are held to 8 waves
@@ -564,8 +580,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void
 render_refill_batch_kernel(FrameDesc single, const FrameDesc *__restrict__ table,
                            const LaunchHeader *__restrict__ hdr, int nframes,
                            uint32_t total_tiles, uint32_t *__restrict__ counter, int TW, int TH) {
-  refill_body<NORM, AXIS, true, COUNT, STICKY, GUIDED>(single, table, hdr, nframes, total_tiles,
-                                                       counter, TW, TH);
+  refill_body<NORM, AXIS, true, COUNT, STICKY, GUIDED ? kHandGuided : kHandOne>(
+      single, table, hdr, nframes, total_tiles, counter, TW, TH);
 }
 
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
