@@ -169,7 +169,8 @@ def _tail(recs, keys, q=0.99):
     return out
 
 
-def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=None, slots=0):
+def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=None, slots=0,
+                epoch_work=0.0):
     """The request stream replayed against the server (continuous batching; split
     precision, the stream's own, and FP32) and against the plain path (one FP32 dqj_render
     at a time, FIFO).
@@ -181,7 +182,8 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
     queue wait (arrival to the start of its render) and render. The p99 tail is reported
     with the mean of each component. Closed loop ("capacity"): the first capacity_n
     requests submitted back to back; throughput = requests, pixels and GPU-counted DQ
-    updates over the makespan.
+    updates over the makespan. The latency streams run without the update counter, as a
+    production server would (the counting kernels are slower); the capacity runs count.
     """
     import threading
     import queue as q
@@ -189,8 +191,9 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
     stream = workloads.serve_stream(duration_s=duration_s, rate_hz=rate_hz)
     policy = dqj.SERVE_FAIR if policy is None else policy
 
-    def served(arrivals, open_loop, precision=workloads.PREC_SPLIT):
-        srv = dqj.Server(precision=precision, count_iters=True, policy=policy, slots=slots)
+    def served(arrivals, open_loop, precision=workloads.PREC_SPLIT, count=False):
+        srv = dqj.Server(precision=precision, count_iters=count, policy=policy, slots=slots,
+                         epoch_work=epoch_work)
         pend = q.Queue()
         t0 = time.monotonic() + 0.05
 
@@ -202,7 +205,10 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
                     if dt > 0:
                         time.sleep(dt)
                 out = dqj.alloc_outputs(a.params.width, a.params.height, extras=False)
-                cur.synchronize()   # the zeroed work counter must be in place before the server adds to it
+                if count:
+                    cur.synchronize()   # the zeroed work counter must be in place before the server adds to it
+                else:
+                    del out["iters"]
                 p = a.params.replace(precision=precision)
                 tk = srv.submit(p, out)
                 pend.put((tk, (t0 + a.t) if open_loop else time.monotonic(), out, p))
@@ -226,17 +232,18 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
             if len(recs) % 2000 == 0:
                 progress(f"served ({'split' if precision == workloads.PREC_SPLIT else 'FP32'}): "
                          f"{len(recs)} of {len(arrivals)} requests done")
-            counters.append(out["iters"])   # summed once at the end, off the critical path
+            if count:
+                counters.append(out["iters"])   # summed once at the end, off the critical path
             pixels += p.pixels
             n += 1
         th.join()
         end = time.monotonic()
-        iters = int(torch.stack(counters).sum().item())
+        iters = int(torch.stack(counters).sum().item()) if count else None
         st = srv.stats()
         srv.close()
         return recs, iters, pixels, n, end - start, st
 
-    def plain(arrivals, open_loop):
+    def plain(arrivals, open_loop, count=False):
         s = torch.cuda.current_stream()
         t0 = time.monotonic() + 0.05
         recs, counters, pixels = [], [], 0
@@ -251,6 +258,8 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
             else:
                 t_arr = time.monotonic()
             out = dqj.alloc_outputs(p.width, p.height, extras=False)
+            if not count:
+                del out["iters"]
             t_start = time.monotonic()
             dqj.render(p, out=out, stream=s)
             s.synchronize()
@@ -259,10 +268,11 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
                          "side": p.width, "max_iter": p.max_iter})
             if len(recs) % 2000 == 0:
                 progress(f"plain: {len(recs)} of {len(arrivals)} requests done")
-            counters.append(out["iters"])
+            if count:
+                counters.append(out["iters"])
             pixels += p.pixels
         dur = time.monotonic() - start
-        return recs, int(torch.stack(counters).sum().item()), pixels, len(arrivals), dur
+        return recs, int(torch.stack(counters).sum().item()) if count else None, pixels, len(arrivals), dur
 
     served_keys = ("admit_wait", "first_launch_wait", "run")
     res = {"stream": f"Poisson {rate_hz:g} req/s for {duration_s:g} s ({len(stream)} requests), "
@@ -270,7 +280,8 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
                      "march steps 16*max_iter, 10 bisection steps",
            "requests": len(stream),
            "policy": "oldest first" if policy == dqj.SERVE_OLDEST else "fair share",
-           "slots": slots or 3}
+           "slots": slots or 3, "epoch_work": epoch_work or 8e9,
+           "latency_runs": "without the update counter; capacity runs count"}
     progress(f"serve stream of {len(stream)} requests: split server, FP32 server, plain")
     sr, si, sp, sn, sdur, sst = served(stream, True)
     res["served"] = {"precision": "split (FP16 march, FP32 re-check and bisection, FP64 re-bisection)",
@@ -283,9 +294,9 @@ def serve_bench(duration_s, rate_hz, capacity_n, dqj, workloads, torch, policy=N
                     **_tail(pr, ("queue_wait", "render"))}
     progress(f"capacity: {capacity_n} requests back to back, each way")
     cap = stream[:capacity_n]
-    cl, ci, cp, cn, cdur, _ = served(cap, False)
-    gl, gi, gp, gn, gdur, _ = served(cap, False, workloads.PREC_FP32)
-    ql, qi, qp, qn, qdur = plain(cap, False)
+    cl, ci, cp, cn, cdur, _ = served(cap, False, count=True)
+    gl, gi, gp, gn, gdur, _ = served(cap, False, workloads.PREC_FP32, count=True)
+    ql, qi, qp, qn, qdur = plain(cap, False, count=True)
     res["capacity"] = {
         "requests": cn,
         "served": {"req_per_s": cn / cdur, "mpix_per_s": cp / cdur / 1e6,
@@ -681,6 +692,8 @@ def main():
                     help="length of the served request stream (0: skip)")
     ap.add_argument("--serve-policy", choices=["fair", "oldest"], default="fair")
     ap.add_argument("--serve-slots", type=int, default=0, help="epoch slots (0: the library default)")
+    ap.add_argument("--serve-epoch-work", type=float, default=0.0,
+                    help="estimated DQ updates per epoch (0: the library default, 8e9)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--capacity-requests", type=int, default=300)
     ap.add_argument("--workload", choices=["plain_1024", "split_1080p", "sweep_256", "de_1024",
@@ -823,7 +836,7 @@ def main():
         line["serve"] = serve_bench(args.serve_seconds, args.serve_rate, args.capacity_requests,
                                     dqj, workloads, torch,
                                     dqj.SERVE_OLDEST if args.serve_policy == "oldest" else dqj.SERVE_FAIR,
-                                    args.serve_slots)
+                                    args.serve_slots, args.serve_epoch_work)
     if not args.no_cpu:
         progress("CPU baseline: the FP64 oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline(ps, args.cpu_seconds)
