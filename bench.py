@@ -322,13 +322,16 @@ def frame_error(p, g, pixels, oracle_mod):
     gs = g["shade"].reshape(-1)[pixels].astype(np.float64)
     E = workloads.scene_extent(p)
     both = gm & om
-    dd = np.abs(np.where(both, gd - o["depth"], 0.0))
+    dd = np.zeros(len(pixels))
+    dd[both] = np.abs(gd[both] - o["depth"][both])   # (misses hold +inf)
     agree = (~gm & ~om) | (both & (dd <= 1e-4 * E))
     ok = both & agree
     ds = np.abs(gs - o["shade"])[ok]
     return {"pixels": int(len(pixels)), "mask_agree": float(agree.mean()),
+            "mask_disagree_pixels": int((gm != om).sum()),
             "hits_gpu": int(gm.sum()), "hits_oracle": int(om.sum()),
             "depth_err_max_E": float(dd[ok].max() / E) if ok.any() else 0.0,
+            "depth_err_mean_E": float(dd[ok].mean() / E) if ok.any() else 0.0,
             "shade_err_max": float(ds.max()) if ok.any() else 0.0,
             "shade_within_1_255": float((ds <= 1 / 255).mean()) if ok.any() else 1.0}
 
@@ -377,16 +380,20 @@ def bench_split(args, dqj, workloads, torch):
     c32.close()
     t_fp32 = timed_plan(dqj, torch, ps32, [{k: v for k, v in o.items() if k != "iters"} for o in outs32],
                         args.steps, args.warmup)
-    # error of every frame against the FP64 oracle on sampled pixels (uniform + GPU hits)
+    # error of every frame against the FP64 oracle on sampled pixels (uniform + GPU hits),
+    # for the split form and for the FP32 path on the same pixels
     rng = np.random.default_rng(7)
-    errors = []
-    for p, o in zip(ps, outs):
+    errors, errors32 = [], []
+    for p, o, o32 in zip(ps, outs, outs32):
         g = {k: v.cpu().numpy() for k, v in o.items()}
+        g32 = {k: v.cpu().numpy() for k, v in o32.items()}
         pix = rng.choice(p.pixels, args.error_pixels, replace=False)
         h = np.nonzero(g["mask"].reshape(-1))[0]
         if h.size:
             pix = np.union1d(pix, rng.choice(h, min(h.size, args.error_pixels // 2), replace=False))
-        errors.append(frame_error(p, g, np.sort(pix), oracle))
+        pix = np.sort(pix)
+        errors.append(frame_error(p, g, pix, oracle))
+        errors32.append(frame_error(p, g32, pix, oracle))
     ms_split = float(np.median(t_split))
     ms_fp32 = float(np.median(t_fp32))
     # the FP32 path's count is the method's update count (its FP32 classification)
@@ -407,6 +414,7 @@ def bench_split(args, dqj, workloads, torch):
         "speedup_vs_fp32": ms_fp32 / ms_split,
         "pct_fp32_peak_equiv": 100.0 * FLOPS_PER_UPDATE * fp32_iters / (ms_split * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
         "error_vs_fp64_oracle": errors,
+        "fp32_error_vs_fp64_oracle": errors32,
     }
 
 
