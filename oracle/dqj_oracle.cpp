@@ -291,8 +291,12 @@ static int32_t classify_world(const dqjo_params *p, const double x[3], int32_t *
 }
 
 // Normals (section "Lighting/Illumination" samples neighbouring points with a small
-// delta). The sampled field is the smooth escape potential ln||z_m||^2 / 2^m, which
-// is continuous across escape-index changes (and equals 2 ln|x| exactly for c = 0).
+// delta). The sampled field is the escape potential ln||z_m||^2 / 2^m (2 ln|x| exactly
+// for c = 0). Where the norm of a square is the square of the norm (the real-part
+// norm, a zero dual part) it is nearly continuous across escape-index changes. Under
+// the 8-square norm an orbit whose norm nearly reached R in its dual part can fall
+// back, so the potential can jump across the surface, and a stencil across the jump
+// tilts the normal.
 // For a projection the field is the least potential over the fibre points (the
 // potential of the union of the fibre's inside sets), and *m the updates over all F.
 double dqjo_potential(const dqjo_params *p, const double x[3], int32_t *m) {

@@ -31,8 +31,10 @@
  * forms of the iteration, the render (ball, and the quadric of a general affine slice
  * with its origin and axis order) and the projection (union of shifted balls, least
  * potential over the fibre), the quaternion and complex reductions, symmetries, the
- * dual part as a derivative, and brute-force marches. Parity unpinned: shading for
- * c != 0 (no closed form; the GPU is checked against this oracle only).
+ * dual part as a derivative, brute-force marches, and for c != 0 the normal and shade
+ * against the traced surface's own normal where the potential is smooth. Parity
+ * unpinned: the normal where a stencil straddles a jump of the potential (no
+ * independent value; the GPU is checked against this oracle only).
  */
 #ifndef DQJ_ORACLE_H
 #define DQJ_ORACLE_H
