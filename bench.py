@@ -45,8 +45,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/tile_order.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "97078aa7dc3bcc07b44863a8cc1f1a140aa179b28da3b3c45bd3b05caef0ce24",
-        "fetch_kib": 102.96, "fetch_factor": 2.0, "write_kib": 38256.84, "write_factor": 1.0,
+        "sources_sha256": "86d67b8d9c82383e7554bfab0a688fd1e5a41ee87a350ba0da0fc4c8ad1938d0",
+        "fetch_kib": 103.9, "fetch_factor": 2.0, "write_kib": 38278.77, "write_factor": 1.0,
     },
     "voxel": {
         "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
