@@ -45,8 +45,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/tile_order.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "86d67b8d9c82383e7554bfab0a688fd1e5a41ee87a350ba0da0fc4c8ad1938d0",
-        "fetch_kib": 103.9, "fetch_factor": 2.0, "write_kib": 38278.77, "write_factor": 1.0,
+        "sources_sha256": "55664e1d07ba53540131593ecf89f7e0d9402b80ff34752ddccdbae8f57f532d",
+        "fetch_kib": 100.23, "fetch_factor": 2.0, "write_kib": 38250.9, "write_factor": 1.0,
     },
     "voxel": {
         "sources": ["paper_2303_14827_amd/csrc/voxel.hip", "paper_2303_14827_amd/csrc/persist.h",
@@ -54,8 +54,8 @@ TRAFFIC_RECORDS = {
                     "paper_2303_14827_amd/csrc/dq_device.h", "paper_2303_14827_amd/csrc/kparams.h",
                     "paper_2303_14827_amd/csrc/runtime_internal.h", "paper_2303_14827_amd/build.py",
                     "include/dqj.h"],
-        "sources_sha256": "1fb547a59e3418002507913e3bce63569d77e1fc6f8eb5eb14054f85da26c533",
-        "fetch_kib": 621.25, "fetch_factor": 2.0, "write_kib": 1334244.62, "write_factor": 1.0,
+        "sources_sha256": "cd9e1af443f3142322565516528a323878029304a00b17a22d2c6d59e3dbf92a",
+        "fetch_kib": 622.02, "fetch_factor": 2.0, "write_kib": 1336996.35, "write_factor": 1.0,
     },
 }
 

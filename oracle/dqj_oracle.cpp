@@ -297,26 +297,45 @@ static int32_t classify_world(const dqjo_params *p, const double x[3], int32_t *
 // the 8-square norm an orbit whose norm nearly reached R in its dual part can fall
 // back, so the potential can jump across the surface, and a stencil across the jump
 // tilts the normal.
-// For a projection the field is the least potential over the fibre points (the
-// potential of the union of the fibre's inside sets), and *m the updates over all F.
-double dqjo_potential(const dqjo_params *p, const double x[3], int32_t *m) {
+//
+// A potential is held as its two parts: lv = ln(max(||z_m||^2, 1e-30)) and the escape
+// index m (N when inside), the value being lv * 2^-m. For a projection the field is the
+// least potential over the fibre points (the potential of the union of the fibre's
+// inside sets): the parts of the least one, and *total the updates over all F.
+static void potential_parts(const dqjo_params *p, const double x[3], double *lv, int32_t *me,
+                            int32_t *total) {
   double z0[8];
   dqjo_slice_map(p, x, z0);
   const int32_t F = p->fiber_count > 0 ? p->fiber_count : 1;
-  double best = 0.0;
-  int32_t total = 0;
+  int32_t sum = 0;
   for (int32_t f = 0; f < F; ++f) {
     double z[8], zf[8], n2;
     for (int q = 0; q < 8; ++q) z[q] = z0[q] + (p->fiber_count > 0 ? p->fiber[8 * f + q] : 0.0);
     int32_t mi;
     dqjo_classify(p, z, &mi, zf, &n2);
-    total += mi;
+    sum += mi;
     const double v = n2 > 1e-30 ? n2 : 1e-30;
-    const double G = log(v) * ldexp(1.0, -mi);
-    if (f == 0 || G < best) best = G;
+    const double l = log(v);
+    // compare l 2^-mi with the best so far, both scaled by 2^min(mi, me)
+    bool less = f == 0;
+    if (!less) {
+      const int32_t mm = mi < *me ? mi : *me;
+      less = l * ldexp(1.0, mm - mi) < *lv * ldexp(1.0, mm - *me);
+    }
+    if (less) {
+      *lv = l;
+      *me = mi;
+    }
   }
+  *total = sum;
+}
+
+double dqjo_potential(const dqjo_params *p, const double x[3], int32_t *m) {
+  double lv;
+  int32_t me, total;
+  potential_parts(p, x, &lv, &me, &total);
   if (m) *m = total;
-  return best;
+  return lv * ldexp(1.0, -me);
 }
 
 struct PixelResult {
@@ -348,22 +367,34 @@ static double phong(const dqjo_params *p, const double n[3], const double d[3]) 
 // Section "Lighting/Illumination": the normal at a hit point ph is the normalised
 // central difference of the potential along the world axes (the ray's reversed
 // direction where the difference vanishes or is not finite); the shade is Eq. phong.
-// The 6 points' updates are added to *iters.
+// The six potentials are taken relative to their least escape index m0: the difference
+// is formed from lv 2^(m0 - m), which is the potential times 2^m0. A common positive
+// factor leaves the normalised gradient unchanged (exactly, as a power of two), and
+// the scaled terms stay representable at any max_iter: unscaled, 2^-m and its square
+// underflow in double precision once m passes about 537. (When all six points stay
+// inside, the terms are ln||z_N||^2 at full weight: for c = 0 that is 2^(N+1) ln|x|, a
+// radial field; where orbits settle on an attracting cycle, at large max_iter their
+// differences are rounding noise, and so is such a normal.) The 6 points' updates are
+// added to *iters.
 static double hit_normal_shade(const dqjo_params *p, const double d[3], const double ph[3],
                                double n[3], uint64_t *iters) {
-  // Central differences of the potential along the world axes.
-  double g[3];
+  double lv[3][2];
+  int32_t me[3][2];
+  int32_t m0 = 0;
   for (int a = 0; a < 3; ++a) {
-    double xp[3] = {ph[0], ph[1], ph[2]};
-    double xm[3] = {ph[0], ph[1], ph[2]};
-    xp[a] = ph[a] + p->normal_h;
-    xm[a] = ph[a] - p->normal_h;
-    int32_t mp, mm;
-    const double gp = dqjo_potential(p, xp, &mp);
-    const double gm = dqjo_potential(p, xm, &mm);
-    *iters += (uint64_t)mp + (uint64_t)mm;
-    g[a] = gp - gm;
+    for (int s = 0; s < 2; ++s) {
+      double x[3] = {ph[0], ph[1], ph[2]};
+      x[a] = s == 0 ? ph[a] + p->normal_h : ph[a] - p->normal_h;
+      int32_t total;
+      potential_parts(p, x, &lv[a][s], &me[a][s], &total);
+      *iters += (uint64_t)total;
+      if ((a == 0 && s == 0) || me[a][s] < m0) m0 = me[a][s];
+    }
   }
+  // Central differences of the scaled potential along the world axes.
+  double g[3];
+  for (int a = 0; a < 3; ++a)
+    g[a] = lv[a][0] * ldexp(1.0, m0 - me[a][0]) - lv[a][1] * ldexp(1.0, m0 - me[a][1]);
   const double glen = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
   if (glen > 0.0 && isfinite(glen)) {
     n[0] = g[0] / glen;

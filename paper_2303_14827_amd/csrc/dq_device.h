@@ -268,11 +268,55 @@ __device__ __forceinline__ bool clip_box(const KParams &P, const T d[3], T &t0, 
   return true;
 }
 
-// Smooth escape potential ln(max(||z_m||^2, 1e-30)) * 2^-m (m = N when inside).
+// The escape potential ln(max(||z_m||^2, 1e-30)) * 2^-m (m = N when inside) is held as
+// its two parts: pot_log(||z_m||^2) and m.
+template <typename T>
+__device__ __forceinline__ T pot_log(T n2) {
+  return log(n2 > T(1e-30) ? n2 : T(1e-30));
+}
+
+// The potential itself, lv 2^-m, for stencils whose max_iter keeps it and the squares of
+// its differences in range (the lane-refill kernels at small max_iter).
 template <typename T>
 __device__ __forceinline__ T potential(T n2, int m) {
   const T v = n2 > T(1e-30) ? n2 : T(1e-30);
   return log(v) * ldexp(T(1), -m);
+}
+
+// Potential lv1 2^-m1 < lv2 2^-m2, compared with both scaled by 2^min(m1, m2).
+template <typename T>
+__device__ __forceinline__ bool pot_less(T lv1, int m1, T lv2, int m2) {
+  const int mm = m1 < m2 ? m1 : m2;
+  return lv1 * ldexp(T(1), mm - m1) < lv2 * ldexp(T(1), mm - m2);
+}
+
+// One point of the central-difference stencil of the normal: point k (0..5, in the
+// order +x, -x, +y, -y, +z, -z) with potential lv 2^-m. The components carry the
+// potential times 2^m0, m0 being the least escape index of the stencil so far (a
+// smaller one rescales them by a power of two, exactly). The normalised gradient does
+// not see that common factor, and the scaled terms stay representable at any max_iter:
+// unscaled, 2^-m flushes to zero in FP32 beyond m = 126, and the squares of the
+// differences of a smooth stencil beyond about m = 53.
+template <typename T>
+__device__ __forceinline__ void stencil_add(T &gx, T &gy, T &gz, int &m0, int k, T lv, int m) {
+  if (k == 0) {
+    m0 = m;
+  } else if (m < m0) {
+    const T s = ldexp(T(1), m - m0);
+    gx *= s;
+    gy *= s;
+    gz *= s;
+    m0 = m;
+  }
+  const T G = lv * ldexp(T(1), m0 - m);
+  const T sg = (k & 1) ? -G : G;
+  const int axis = k >> 1;
+  if (axis == 0)
+    gx += sg;
+  else if (axis == 1)
+    gy += sg;
+  else
+    gz += sg;
 }
 
 // Outputs of one pixel.

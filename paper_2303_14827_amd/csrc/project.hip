@@ -108,28 +108,37 @@ __device__ __forceinline__ bool inside_union(const KParams &P, const QC &K, cons
 }
 
 // Least escape potential over the fibre points of world point (x, y, w), on every lane
-// of the group.
+// of the group, as its two parts (*lv, the return value m; see stencil_add). A lane
+// without fibre points starts from (+inf, 0), which every point's potential is below.
 template <int NORM, int L, bool COUNT>
-__device__ __forceinline__ float potential_union(const KParams &P, const QC &K, const FiberLds &fl,
-                                                 int F, int sub,
-                                                 float x, float y, float w,
-                                                 unsigned long long &iters) {
+__device__ __forceinline__ int potential_union(const KParams &P, const QC &K, const FiberLds &fl,
+                                               int F, int sub, float x, float y, float w,
+                                               unsigned long long &iters, float *lv) {
   const DQ<float> z0 = slice_map<float>(P, x, y, w);
   float best = __builtin_huge_valf();
+  int best_m = 0;
   for (int f = sub; f < F; f += L) {
     float n2;
     int m = classify_q<NORM>(offset_point(z0, fl, f), K, P.N, &n2);
     m = m ? m : P.N;
     if constexpr (COUNT) iters += m;
-    const float G = potential(n2, m);
-    best = G < best ? G : best;
+    const float l = pot_log(n2);
+    if (pot_less(l, m, best, best_m)) {
+      best = l;
+      best_m = m;
+    }
   }
 #pragma unroll
   for (int s = 1; s < L; s <<= 1) {
     const float o = __shfl_xor(best, s, 64);
-    best = o < best ? o : best;
+    const int om = __shfl_xor(best_m, s, 64);
+    if (pot_less(o, om, best, best_m)) {
+      best = o;
+      best_m = om;
+    }
   }
-  return best;
+  *lv = best;
+  return best_m;
 }
 
 template <int NORM, int L, bool COUNT>
@@ -176,15 +185,17 @@ __device__ void render_pixel_project(const KParams &P, const QC &K, const FiberL
   const float ph[3] = {fmaf(thit, d[0], P.eye[0]), fmaf(thit, d[1], P.eye[1]),
                        fmaf(thit, d[2], P.eye[2])};
   float g[3] = {0.0f, 0.0f, 0.0f};
+  int m0 = 0;
   // (the four-neighbour normal is formed after the frame: no stencil here)
   if (P.normal_mode == 0) {
     for (int a = 0; a < 3; ++a) {
-      float x[3] = {ph[0], ph[1], ph[2]};
-      x[a] = ph[a] + P.h;
-      const float gp = potential_union<NORM, L, COUNT>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
-      x[a] = ph[a] - P.h;
-      const float gm = potential_union<NORM, L, COUNT>(P, K, fl, F, sub, x[0], x[1], x[2], iters);
-      g[a] = gp - gm;
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        float x[3] = {ph[0], ph[1], ph[2]};
+        x[a] = sgn == 0 ? ph[a] + P.h : ph[a] - P.h;
+        float lv;
+        const int m = potential_union<NORM, L, COUNT>(P, K, fl, F, sub, x[0], x[1], x[2], iters, &lv);
+        stencil_add(g[0], g[1], g[2], m0, 2 * a + sgn, lv, m);
+      }
     }
   }
   finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);

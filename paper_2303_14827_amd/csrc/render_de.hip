@@ -173,11 +173,11 @@ __device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j,
   const float ph[3] = {fmaf(thit, d[0], P.eye[0]), fmaf(thit, d[1], P.eye[1]),
                        fmaf(thit, d[2], P.eye[2])};
   float g[3] = {0.0f, 0.0f, 0.0f};
+  int m0 = 0;
   // (the four-neighbour normal is formed after the frame: no stencil here)
   if (P.normal_mode == 0)
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float gp = 0.0f;
 #pragma unroll
     for (int sgn = 0; sgn < 2; ++sgn) {
       float x[3] = {ph[0], ph[1], ph[2]};
@@ -188,10 +188,8 @@ __device__ void render_pixel_de(const KParams &P, const QConst &K, int i, int j,
       int m = classify_de<NORM, false>(P, K, z, q, &unused, &n2);
       m = m ? m : P.N;
       if constexpr (COUNT) iters += m;
-      const float G = potential(n2, m);
-      gp = sgn == 0 ? G : gp - G;
+      stencil_add(g[0], g[1], g[2], m0, 2 * a + sgn, pot_log(n2), m);
     }
-    g[a] = gp;
   }
   finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
 }
@@ -450,16 +448,8 @@ __global__ __launch_bounds__(1024) void render_de_refill_kernel(FrameDesc single
           tr = 0.5f * (lo + hi);
           restart = true;
         }
-      } else {   // DE_NORMAL: stencil point sidx just retired
-        const float G = potential(n2c + K.h[0], m);
-        const float sg = (sidx & 1) ? -G : G;
-        const int axis = sidx >> 1;
-        if (axis == 0)
-          gx += sg;
-        else if (axis == 1)
-          gy += sg;
-        else
-          gz += sg;
+      } else {   // DE_NORMAL: stencil point sidx just retired (b: least escape index)
+        stencil_add(gx, gy, gz, b, sidx, pot_log(n2c + K.h[0]), m);
         ++sidx;
       }
       if (next_normal) {
@@ -740,16 +730,8 @@ __global__ __launch_bounds__(1024) void render_de_lockstep_kernel(FrameDesc F, u
         thit = 0.5f * (lo + hi);
         next_normal = true;
       }
-    } else if (phase == DE_NORMAL) {
-      const float G = potential(n2, m);
-      const float sg = (sidx & 1) ? -G : G;
-      const int axis = sidx >> 1;
-      if (axis == 0)
-        gx += sg;
-      else if (axis == 1)
-        gy += sg;
-      else
-        gz += sg;
+    } else if (phase == DE_NORMAL) {   // (b: the stencil's least escape index)
+      stencil_add(gx, gy, gz, b, sidx, pot_log(n2), m);
       ++sidx;
     }
     if (next_normal) {

@@ -64,11 +64,11 @@ __device__ void render_pixel_f32(const KParams &P, int i, int j, PixelOut &r,
   const float ph[3] = {fmaf(thit, d[0], P.eye[0]), fmaf(thit, d[1], P.eye[1]),
                        fmaf(thit, d[2], P.eye[2])};
   float g[3] = {0.0f, 0.0f, 0.0f};
+  int m0 = 0;
   // (the four-neighbour normal is formed after the frame: no stencil here)
   if (P.normal_mode == 0)
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float gp = 0.0f;
 #pragma unroll
     for (int sgn = 0; sgn < 2; ++sgn) {
       float x[3] = {ph[0], ph[1], ph[2]};
@@ -78,10 +78,8 @@ __device__ void render_pixel_f32(const KParams &P, int i, int j, PixelOut &r,
       int m = dq_classify<NORM>(z, c, P.N, P.R2, &n2);
       m = m ? m : P.N;
       iters += m;
-      const float G = potential(n2, m);
-      gp = sgn == 0 ? G : gp - G;
+      stencil_add(g[0], g[1], g[2], m0, 2 * a + sgn, pot_log(n2), m);
     }
-    g[a] = gp;
   }
   finish_hit(P, g, d, thit, kstar, (uint8_t)(DQJ_FLAG_BOX | DQJ_FLAG_HIT), r);
 }

@@ -60,7 +60,7 @@ __device__ __forceinline__ void start_point(const KParams &P, float x, float y, 
 // are handed out: one per atomic, guided chunks, or a first tile per wave without the
 // counter; see the hand-out).
 enum { kHandOne = 0, kHandGuided = 1, kHandFirst = 2 };
-template <int NORM, bool AXIS, bool BATCH, bool COUNT, bool STICKY, int HAND>
+template <int NORM, bool AXIS, bool BATCH, bool COUNT, bool STICKY, int HAND, bool WIDE>
 __device__ __forceinline__ void refill_body(const FrameDesc &single,
                                             const FrameDesc *__restrict__ table,
                                             const LaunchHeader *__restrict__ hdr, int nframes,
@@ -219,15 +219,20 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
           restart = true;
         }
       } else {  // PH_NORMAL: stencil point sidx just retired
-        const float G = potential(n2c + h[0], m);
-        const float sg = (sidx & 1) ? -G : G;
-        const int axis = sidx >> 1;
-        if (axis == 0)
-          gx += sg;
-        else if (axis == 1)
-          gy += sg;
-        else
-          gz += sg;
+        if constexpr (WIDE) {
+          // (b, the bisection counter, holds the stencil's least escape index here)
+          stencil_add(gx, gy, gz, b, sidx, pot_log(n2c + h[0]), m);
+        } else {   // max_iter <= kUnscaledMaxIter: the potentials as they are
+          const float G = potential(n2c + h[0], m);
+          const float sg = (sidx & 1) ? -G : G;
+          const int axis = sidx >> 1;
+          if (axis == 0)
+            gx += sg;
+          else if (axis == 1)
+            gy += sg;
+          else
+            gz += sg;
+        }
         ++sidx;
       }
       if (next_normal) {
@@ -510,16 +515,20 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
           tr = 0.5f * (lo + hi);
           restart = true;
         }
-      } else {  // PH_NORMAL: stencil point sidx just retired
-        const float G = potential(n2c + h[0], m);
-        const float sg = (sidx & 1) ? -G : G;
-        const int axis = sidx >> 1;
-        if (axis == 0)
-          gx += sg;
-        else if (axis == 1)
-          gy += sg;
-        else
-          gz += sg;
+      } else {  // PH_NORMAL: stencil point sidx just retired (as in the loop above)
+        if constexpr (WIDE) {
+          stencil_add(gx, gy, gz, b, sidx, pot_log(n2c + h[0]), m);
+        } else {
+          const float G = potential(n2c + h[0], m);
+          const float sg = (sidx & 1) ? -G : G;
+          const int axis = sidx >> 1;
+          if (axis == 0)
+            gx += sg;
+          else if (axis == 1)
+            gy += sg;
+          else
+            gz += sg;
+        }
         ++sidx;
       }
       if (next_normal) {
@@ -594,32 +603,32 @@ __device__ __forceinline__ void refill_body(const FrameDesc &single,
 }
 
 // Single-frame launches: the frame record is a kernel argument.
-template <int NORM, bool AXIS, bool COUNT, bool STICKY>
+template <int NORM, bool AXIS, bool COUNT, bool STICKY, bool WIDE>
 __global__ __launch_bounds__(1024) void render_refill_kernel(FrameDesc single,
                                                              const FrameDesc *__restrict__ table,
                                                              const LaunchHeader *__restrict__ hdr,
                                                              int nframes, uint32_t total_tiles,
                                                              uint32_t *__restrict__ counter,
                                                              int TW, int TH) {
-  refill_body<NORM, AXIS, false, COUNT, STICKY, kHandFirst>(single, table, hdr, nframes,
-                                                            total_tiles, counter, TW, TH);
+  refill_body<NORM, AXIS, false, COUNT, STICKY, kHandFirst, WIDE>(single, table, hdr, nframes,
+                                                                  total_tiles, counter, TW, TH);
 }
 
 // Batched launches (frames from a device table: the throughput path) are held to 8 waves
 // per SIMD. Their allocation then fits 64 VGPRs without spilling; left free, rare code
 // of the slow path and the ray set-up pushes it to 65-69 and the occupancy to 7.
-template <int NORM, bool AXIS, bool COUNT, bool STICKY, bool GUIDED>
+template <int NORM, bool AXIS, bool COUNT, bool STICKY, bool GUIDED, bool WIDE>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void
 render_refill_batch_kernel(FrameDesc single, const FrameDesc *__restrict__ table,
                            const LaunchHeader *__restrict__ hdr, int nframes,
                            uint32_t total_tiles, uint32_t *__restrict__ counter, int TW, int TH) {
-  refill_body<NORM, AXIS, true, COUNT, STICKY, GUIDED ? kHandGuided : kHandOne>(
+  refill_body<NORM, AXIS, true, COUNT, STICKY, GUIDED ? kHandGuided : kHandOne, WIDE>(
       single, table, hdr, nframes, total_tiles, counter, TW, TH);
 }
 
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
-template <bool BATCH, bool COUNT>
+template <bool BATCH, bool COUNT, bool WIDE>
 static void launch_refill_variant(const FrameDesc &single, const FrameDesc *table,
                                   const LaunchHeader *hdr, int nframes,
                                   uint32_t total_tiles, int norm, int mode, uint32_t *counter,
@@ -635,19 +644,20 @@ static void launch_refill_variant(const FrameDesc &single, const FrameDesc *tabl
   do {                                                                                         \
     if constexpr (BATCH) {                                                                     \
       if (guided)                                                                              \
-        hipLaunchKernelGGL((render_refill_batch_kernel<NM, AX, COUNT, ST, !COUNT>), dim3(blocks), \
+        hipLaunchKernelGGL((render_refill_batch_kernel<NM, AX, COUNT, ST, !COUNT, WIDE>), dim3(blocks), \
                            dim3(threads), 0, stream, single, table, hdr, nframes, total_tiles, \
                            counter, s.tile_w, s.tile_h);                                       \
       else                                                                                     \
-        hipLaunchKernelGGL((render_refill_batch_kernel<NM, AX, COUNT, ST, false>), dim3(blocks), \
+        hipLaunchKernelGGL((render_refill_batch_kernel<NM, AX, COUNT, ST, false, WIDE>), dim3(blocks), \
                            dim3(threads), 0, stream, single, table, hdr, nframes, total_tiles, \
                            counter, s.tile_w, s.tile_h);                                       \
     } else                                                                                     \
-      hipLaunchKernelGGL((render_refill_kernel<NM, AX, COUNT, ST>), dim3(blocks), dim3(threads), \
+      hipLaunchKernelGGL((render_refill_kernel<NM, AX, COUNT, ST, WIDE>), dim3(blocks), dim3(threads), \
                          0, stream, single, table, hdr, nframes, total_tiles, counter,         \
                          s.tile_w, s.tile_h);                                                  \
   } while (0)
   // counting launches test every first update, so they never take the STICKY variant
+  mode &= kSliceMask;
   if (COUNT && mode == kSliceIdentitySticky) mode = kSliceIdentity;
   if (norm == 0) {
     if (mode == kSliceGeneral)
@@ -676,21 +686,35 @@ static hipError_t launch_refill_impl(const FrameDesc &single, const FrameDesc *t
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
   const int threads = 64 * s.waves_per_block;
   const int blocks = cus * s.blocks_per_cu;
-  if (count)
-    launch_refill_variant<BATCH, true>(single, table, hdr, nframes, total_tiles, norm, mode, counter,
-                                       s, blocks, threads, stream);
-  else
-    launch_refill_variant<BATCH, false>(single, table, hdr, nframes, total_tiles, norm, mode, counter,
-                                        s, blocks, threads, stream);
+#define DQJ_VARIANT(CT, WD)                                                                 \
+  launch_refill_variant<BATCH, CT, WD>(single, table, hdr, nframes, total_tiles, norm, mode, counter, \
+                                       s, blocks, threads, stream)
+  const bool wide = (mode & kModeWide) != 0;
+  if (count) {
+    if (wide)
+      DQJ_VARIANT(true, true);
+    else
+      DQJ_VARIANT(true, false);
+  } else {
+    if (wide)
+      DQJ_VARIANT(false, true);
+    else
+      DQJ_VARIANT(false, false);
+  }
+#undef DQJ_VARIANT
   return hipGetLastError();
 }
 
 int slice_mode_of(const KParams &P) {
-  if (!P.axis_slice) return kSliceGeneral;
-  return P.sticky1 ? kSliceIdentitySticky : kSliceIdentity;
+  const int wide = P.N > kUnscaledMaxIter ? kModeWide : 0;
+  if (!P.axis_slice) return kSliceGeneral | wide;
+  return (P.sticky1 ? kSliceIdentitySticky : kSliceIdentity) | wide;
 }
 
-int combine_slice_mode(int a, int b) { return a < b ? a : b; }
+int combine_slice_mode(int a, int b) {
+  const int sa = a & kSliceMask, sb = b & kSliceMask;
+  return (sa < sb ? sa : sb) | ((a | b) & kModeWide);
+}
 
 hipError_t launch_render_refill(const FrameDesc &frame, uint32_t *counter, const Sched &s, int cus,
                                 hipStream_t stream) {

@@ -40,8 +40,9 @@ struct Slot {
   void *scratch = nullptr;        // split lists or the tile counter
   void *staging = nullptr;        // pinned copy of [header | table]
   // one graph per slice mode: general, identity, identity with untested first update
-  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  // one per launch mode: slice mode (0-2), plus 3 with kModeWide
+  hipGraph_t graph[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool busy = false;
   uint64_t epoch = 0;
 };
@@ -95,7 +96,7 @@ size_t slot_dev_bytes(int max_chunks) {
 void free_slots(dqj_server *s) {
   for (Slot &sl : s->slots) {
     if (sl.busy && sl.done) (void)hipEventSynchronize(sl.done);
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 6; ++a) {
       if (sl.exec[a]) (void)hipGraphExecDestroy(sl.exec[a]);
       if (sl.graph[a]) (void)hipGraphDestroy(sl.graph[a]);
     }
@@ -108,23 +109,24 @@ void free_slots(dqj_server *s) {
   s->slots.clear();
 }
 
-// Capture the slot's graphs (one per slice mode): a counter/list reset and the
-// persistent kernels, which take the epoch's size from the header in device memory.
-// (The split-precision march has no untested-first-update form: its last two graphs
-// are the same.)
+// Capture the slot's graphs (one per launch mode: slice mode a % 3, with kModeWide from
+// a = 3 on): a counter/list reset and the persistent kernels, which take the epoch's size
+// from the header in device memory. (The split-precision march has no untested-first-
+// update form and one stencil sum: its graphs repeat.)
 hipError_t capture_slot(dqj_server *s, Slot &sl) {
   const LaunchHeader *hdr = (const LaunchHeader *)sl.dev;
   const FrameDesc *table = (const FrameDesc *)((char *)sl.dev + sizeof(LaunchHeader));
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 6; ++a) {
+    const int mode = (a % 3) | (a >= 3 ? kModeWide : 0);
     hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le;
     if (s->precision == DQJ_PREC_SPLIT)
-      le = launch_render_split_batch(table, hdr, 0, 0, s->norm, a >= 1, s->count,
+      le = launch_render_split_batch(table, hdr, 0, 0, s->norm, a % 3 >= 1, s->count,
                                      split_scratch_at(sl.scratch, s->epoch_pixels), s->sched,
                                      s->cus, sl.stream);
     else
-      le = launch_render_refill_batch(table, hdr, 0, 0, s->norm, a, s->count,
+      le = launch_render_refill_batch(table, hdr, 0, 0, s->norm, mode, s->count,
                                       (uint32_t *)sl.scratch, s->sched, s->cus, sl.stream);
     e = hipStreamEndCapture(sl.stream, &sl.graph[a]);
     if (le != hipSuccess) return le;
@@ -156,7 +158,8 @@ hipError_t launch_epoch(dqj_server *s, Slot &sl, const serve::Epoch &ep) {
   h->total_tiles = tile;
   const size_t bytes = sizeof(LaunchHeader) + sizeof(FrameDesc) * ep.chunks.size();
   hipError_t e = hipMemcpyAsync(sl.dev, sl.staging, bytes, hipMemcpyHostToDevice, sl.stream);
-  if (e == hipSuccess) e = hipGraphLaunch(sl.exec[mode], sl.stream);
+  const int g = (mode & kSliceMask) + ((mode & kModeWide) ? 3 : 0);
+  if (e == hipSuccess) e = hipGraphLaunch(sl.exec[g], sl.stream);
   if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
   if (e == hipSuccess) {
     sl.busy = true;

@@ -177,9 +177,9 @@ __device__ __forceinline__ uint32_t finish_ray(const P_T &P, const T *c, int N, 
     thit = T(0.5) * (lo + hi);
   }
   T g[3] = {T(0), T(0), T(0)};
+  int m0 = 0;
   // (the four-neighbour normal is formed after the frame: no stencil here)
   for (int a = 0; a < 3 && P.normal_mode == 0; ++a) {
-    T gp = T(0);
     for (int sg = 0; sg < 2; ++sg) {
       const T hs = sg == 0 ? h : -h;
       bool in;
@@ -187,10 +187,8 @@ __device__ __forceinline__ uint32_t finish_ray(const P_T &P, const T *c, int N, 
       const int m = classify_t<NORM>(P, c, N, R2, thit, d, a == 0 ? hs : T(0), a == 1 ? hs : T(0),
                                      a == 2 ? hs : T(0), &in, &n2);
       it += m;
-      const T G = potential(n2, m);
-      gp = sg == 0 ? G : gp - G;
+      stencil_add(g[0], g[1], g[2], m0, 2 * a + sg, pot_log(n2), m);
     }
-    g[a] = gp;
   }
   // shade with this precision's light and coefficients
   const T gl = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -650,16 +648,8 @@ __global__ __launch_bounds__(256) void verify_fp32_kernel(FrameDesc single,
         else
           lo = tm;
         ++b;
-      } else {   // VP_NORMAL: stencil point sidx just retired
-        const float G = potential(n2 + h[0], m);
-        const float sg = (sidx & 1) ? -G : G;
-        const int axis = sidx >> 1;
-        if (axis == 0)
-          gx += sg;
-        else if (axis == 1)
-          gy += sg;
-        else
-          gz += sg;
+      } else {   // VP_NORMAL: stencil point sidx just retired (b: least escape index)
+        stencil_add(gx, gy, gz, b, sidx, pot_log(n2 + h[0]), m);
         ++sidx;
       }
       // the window after k32 is confirmed: bracket the crossing

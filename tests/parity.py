@@ -49,9 +49,11 @@ def shade_explained(p, pix: int, t_gpu: float, t_ora: float, s_gpu: float, n: in
 
 
 def compare(p, gpu: Dict[str, np.ndarray], ora: Dict[str, np.ndarray],
-            pixels: Optional[np.ndarray] = None, scan: bool = True, max_scan: int = 400):
-    """Compare GPU outputs (full images) with oracle outputs (full images, or flat
-    arrays for the listed ``pixels``). Returns a report dict."""
+            pixels: Optional[np.ndarray] = None, scan: bool = True, max_scan: int = 400,
+            gathered: bool = False):
+    """Compare GPU outputs (full images; with ``gathered``, flat arrays already taken at
+    the listed ``pixels``) with oracle outputs (full images, or flat arrays for the listed
+    ``pixels``). Returns a report dict."""
     E = workloads.scene_extent(p)
     tol = 1e-4 * E
     if pixels is None:
@@ -61,8 +63,12 @@ def compare(p, gpu: Dict[str, np.ndarray], ora: Dict[str, np.ndarray],
         idx = np.arange(p.width * p.height)
     else:
         idx = np.asarray(pixels)
-        g = {k: np.asarray(gpu[k]).reshape(-1, *np.asarray(gpu[k]).shape[2:])[idx] for k in
-             ("mask", "depth", "shade", "first_hit") if k in gpu}
+        if gathered:
+            g = {k: np.asarray(gpu[k]).reshape(idx.size) for k in
+                 ("mask", "depth", "shade", "first_hit") if k in gpu}
+        else:
+            g = {k: np.asarray(gpu[k]).reshape(-1, *np.asarray(gpu[k]).shape[2:])[idx] for k in
+                 ("mask", "depth", "shade", "first_hit") if k in gpu}
         o = {k: np.asarray(ora[k]) for k in g}
     gm = g["mask"].astype(bool)
     om = o["mask"].astype(bool)

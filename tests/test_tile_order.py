@@ -41,8 +41,21 @@ int main() {
   long bad = 0;
   for (int X = 1; X <= 64; ++X)
     for (int Y = 1; Y <= 64; ++Y) bad += check(X, Y);
-  const int big[][2] = {{240, 135}, {135, 240}, {128, 128}, {1024, 1024}, {4096, 3}, {3, 4096}};
+  // up to the grids of the largest frame sides (16384) in 8 x 8 tiles, and of a
+  // 16384-pixel row or column in single-pixel tiles
+  const int big[][2] = {{240, 135}, {135, 240}, {128, 128}, {1024, 1024}, {4096, 3}, {3, 4096},
+                        {2048, 2048}, {16384, 1}, {1, 16384}, {16384, 8}, {8, 16384}};
   for (const auto &g : big) bad += check(g[0], g[1]);
+  // a 16384 x 16384 grid (one-pixel tiles of the largest frame), on a stride: every tile in
+  // range and the ring depth never rising along the order
+  int prev = 1 << 30;
+  for (uint32_t k = 0; k < 16384u * 16384u; k += 4099u) {
+    const uint32_t t = dqj::centre_out_tile(k, 16384, 16384);
+    if (t >= 16384u * 16384u) { ++bad; continue; }
+    const int d = depth((int)(t % 16384u), (int)(t / 16384u), 16384, 16384);
+    if (d > prev) ++bad;
+    prev = d;
+  }
   std::printf("%s %ld\n", bad ? "bad" : "ok", bad);
   return bad ? 1 : 0;
 }
