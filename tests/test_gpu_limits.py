@@ -14,6 +14,10 @@
   hit is rounding noise on either side.
 * Largest march_steps (2^20, with max_iter 2 under the (S + B + 8) N <= 2^30 rule) and the
   largest bisect_steps (64).
+* Voxel grids: 4096 x 4096 x 512 (8.6e9 voxels, past 2^32, so the kernel's 64-bit voxel
+  indices run; 43 GB of mask and escape indices) on sampled voxels, the extreme ones among
+  them, with the update counter against the escape indices summed on the device; and a
+  48^3 grid at max_iter 4096, whole.
 """
 import sys
 
@@ -187,3 +191,59 @@ def test_largest_bisect_steps(dqj, oracle_mod, mode):
     g, o, rep = check_whole(dqj, oracle_mod, p, mode, "B64")
     assert rep["hits_oracle"] > 100, rep
     assert rep["depth_err_max_E"] <= 1e-6, rep   # 64 halvings: limited by the FP32 depth only
+
+
+# ---------------------------------------------------------------- voxel grids
+
+def test_grid_past_32_bit_indices(dqj, oracle_mod):
+    import torch
+    p, _ = workloads.voxel_grid(8)
+    dims = (4096, 4096, 512)
+    nvox = dims[0] * dims[1] * dims[2]
+    assert nvox > 1 << 32
+    say("limits grid", dims)
+    r = dqj.classify_grid(p, *dims, extras=True)
+    torch.cuda.synchronize()
+    mask, esc = r["mask"].reshape(-1), r["escape"].reshape(-1)
+    # the counter is the escape indices (max_iter inside) summed, here in slices on the device
+    total = 0
+    step = 1 << 30
+    for a in range(0, nvox, step):
+        m, e = mask[a:a + step], esc[a:a + step]
+        total += int(torch.where(m == 1, torch.full_like(e, p.max_iter), e).sum(dtype=torch.int64))
+    say("  counter", int(r["iters"][0]), "sum", total, "inside", int(mask.sum(dtype=torch.int64)))
+    assert int(r["iters"][0]) == total
+    rng = np.random.default_rng(9)
+    lo = nvox // 2 - (1 << 29)   # inside voxels of the middle slices, across voxel 2^32
+    inside = torch.nonzero(mask[lo:lo + (1 << 30)]).reshape(-1)
+    pick = inside[torch.from_numpy(rng.choice(int(inside.numel()), 3000, replace=False))
+                  .to(inside.device)].cpu().numpy() + lo
+    extremes = np.array([0, dims[0] - 1, dims[0] * dims[1] - 1, (1 << 32) - 1, 1 << 32, (1 << 32) + 1,
+                         nvox - dims[0], nvox - 1], dtype=np.int64)
+    idx = np.unique(np.concatenate([rng.integers(0, nvox, 20000, dtype=np.int64), pick, extremes]))
+    sel = torch.from_numpy(idx).to(mask.device)
+    g = {"mask": mask[sel].cpu().numpy(), "escape": esc[sel].cpu().numpy()}
+    import test_gpu_grid as T
+    o = oracle_mod.classify_grid(p, *dims, voxels=idx)
+    agree = float(np.mean(g["mask"] == o["inside"]))
+    agree_m = float(np.mean(g["escape"] == o["m"]))
+    bad = np.nonzero(g["mask"] != o["inside"])[0]
+    far = 0
+    if bad.size:
+        x = T.centres(p, *dims, idx[bad[:200]])
+        far = int(np.sum(~T.near_boundary(oracle_mod, p, x, o["inside"][bad[:200]])))
+    say("  ", {"voxels": int(idx.size), "inside_oracle": int(o["inside"].sum()), "class_agree": agree,
+               "escape_index_agree": agree_m, "class_mismatch": int(bad.size), "far": far})
+    assert agree >= 0.999 and agree_m >= 0.999 and far == 0
+    assert int(o["inside"].sum()) > 2000
+
+
+def test_grid_max_iter_4096(dqj):
+    from test_gpu_grid import check_against_oracle
+    p, _ = workloads.voxel_grid(8)
+    p = p.replace(c=[-0.2, 0.1, 0, 0, 0.1, 0, 0, 0], max_iter=4096)
+    say("limits grid N4096")
+    g, o, rep = check_against_oracle(dqj, p, (48, 48, 48))
+    assert rep["inside_oracle"] > 1000, rep
+    gm, ge = g["mask"].reshape(-1), g["escape"].reshape(-1)
+    assert int(g["iters"][0]) == int(np.where(gm == 1, p.max_iter, ge).sum())
