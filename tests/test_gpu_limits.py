@@ -247,3 +247,31 @@ def test_grid_max_iter_4096(dqj):
     assert rep["inside_oracle"] > 1000, rep
     gm, ge = g["mask"].reshape(-1), g["escape"].reshape(-1)
     assert int(g["iters"][0]) == int(np.where(gm == 1, p.max_iter, ge).sum())
+
+
+# ---------------------------------------------------------------- empty inputs
+
+def test_empty_inputs(dqj):
+    """Zero-sized inputs on the device: a batch or a plan of no frames and a grid with a
+    zero side are refused as invalid, and nothing is launched; zero points classify to
+    nothing."""
+    import ctypes as C
+    import torch
+    p = workloads.plain_128(0)[0]
+    arr_p = (dqj.dqj_params * 1)(dqj.make_params(p))
+    arr_o = (dqj.dqj_frame_out * 1)()
+    assert dqj.lib().dqj_render_batch(arr_p, arr_o, 0, None) == dqj.E_INVALID
+    plan = C.c_void_p()
+    assert dqj.lib().dqj_batch_plan_create(arr_p, arr_o, 0, None, None, C.byref(plan)) == \
+        dqj.E_INVALID
+    assert not plan.value
+    mask = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    sp = dqj.make_params(p)
+    for dims in ((0, 4, 4), (4, 0, 4), (4, 4, 0)):
+        assert dqj.lib().dqj_classify_grid(C.byref(sp), *dims, C.c_void_p(mask.data_ptr()), None,
+                                           None, None) == dqj.E_INVALID
+    torch.cuda.synchronize()
+    assert int(mask.sum()) == 0   # untouched
+    esc, n2 = dqj.classify_points(torch.empty((0, 8), dtype=torch.float32, device="cuda"), p)
+    torch.cuda.synchronize()
+    assert esc.numel() == 0 and n2.numel() == 0
